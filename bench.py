@@ -1,0 +1,273 @@
+#!/usr/bin/env python3
+"""Benchmark: symmetric sparse SSYMV / MTTKRP on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--form f32|bf16]
+
+A step is one library call of the hot path over one batch of synthetic
+input: output zeroing plus the symmetric kernel over the canonical entries.
+Inputs are resident in HBM before the timed region starts. The metric is
+effective nnz/s: the number of entries of the fully expanded (non-symmetric)
+tensor, sum over stored entries of N!/prod(m!), divided by the time of a
+step. The JSON line also carries the roofline of the dominant kernel (its
+own duration from HIP events around its launch, on its stream), the same
+call on the non-symmetric comparison kernel, and the FP64 CPU oracle timed
+on this host (one core) on the same workload, with the error of the GPU
+result against it.
+
+Workloads (synthetic, seeded; shaped like the paper's):
+  ssymv_rmat   (default) R-MAT scale 22, n=4,194,304, avg degree 16, upper CSR
+  ssymv_small  n=2,000, ~10 stored entries per row
+  mttkrp3      order 3, I=100,000, 20M canonical entries, R=32
+  mttkrp5      order 5, I=5,000, 5M canonical entries, R=16
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="ssymv_rmat",
+                    choices=["ssymv_rmat", "ssymv_small", "mttkrp3", "mttkrp5"])
+    ap.add_argument("--form", default="bf16", choices=["f32", "bf16"],
+                    help="storage of x / B (arithmetic is FP32 either way)")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target CPU time of the oracle baseline leg")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the non-symmetric comparison kernel")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="run one plain device copy of this many MiB first (scales the "
+                         "HBM byte counters of a rocprofv3 --pmc run)")
+    return ap.parse_args()
+
+
+def src_hash(*names):
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_2406_09266_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel_key, current_hash, launches_bytes):
+    """HBM traffic per launch from the committed rocprofv3 PMC summary, or None
+    if there is none for this kernel or the kernel source changed since."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f).get(kernel_key)
+    if not d or d.get("source_hash") != current_hash:
+        return None
+    return d.get("bytes_per_launch")
+
+
+def timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def kernel_ms(fn, reps):
+    """Average duration of the library's hot-kernel launches inside fn()."""
+    import paper_2406_09266_amd as systec
+    import torch
+    torch.cuda.synchronize()
+    with systec.KernelTimer() as kt:
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+    return kt.total_ms / max(1, kt.launches), kt.launches
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; "
+                          f"--gpus {a.gpus} is not supported (multi-GPU sharding is a design "
+                          "note only, see DESIGN.md)"}))
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    import paper_2406_09266_amd as systec
+    from paper_2406_09266_amd import synth
+
+    dev = torch.device("cuda:0")
+    t_gen = time.perf_counter()
+    w = synth.workload(a.workload)
+    t_gen = time.perf_counter() - t_gen
+    out = {"metric": "sym sparse MTTKRP/SSYMV effective nnz/s + %HBM peak",
+           "unit": "effective nnz/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic (seeded generators; no dataset)"}
+
+    if a.workload.startswith("ssymv"):
+        n, U = w["n"], w["col"].size
+        rp = torch.from_numpy(w["rowptr"]).to(dev)
+        col = torch.from_numpy(w["col"]).to(dev)
+        val = torch.from_numpy(w["val"].astype(np.float32)).to(dev)
+        x32 = torch.from_numpy(w["x"].astype(np.float32)).to(dev)
+        x = systec.quantize_bf16(x32) if a.form == "bf16" else x32
+        y = torch.empty(n, dtype=torch.float32, device=dev)
+        rows = torch.repeat_interleave(torch.arange(n, dtype=torch.int32, device=dev),
+                                       rp[1:] - rp[:-1])
+        hist, eff = systec.expansion_stats([rows, col], n)
+        del rows
+        sx = 2 if a.form == "bf16" else 4
+        b_alg = 4 * (n + 1) + 8 * U + n * sx + 4 * n
+        step = lambda: systec.ssymv(rp, col, val, x, out=y)  # noqa: E731
+        kernel_key, kernel_src = "ssymv", ("ssymv.hip",)
+        cfg = {"workload": a.workload, "n": n, "stored_nnz": U, "effective_nnz": eff,
+               "diagonal_nnz": hist[1], "x_storage": a.form, "accumulate": "f32"}
+    else:
+        order, I = w["order"], w["dim"]
+        R = w["B"].shape[1]
+        nnz = w["val"].size
+        idx = [torch.from_numpy(v).to(dev) for v in w["idx"]]
+        val = torch.from_numpy(w["val"].astype(np.float32)).to(dev)
+        B32 = torch.from_numpy(w["B"].astype(np.float32)).to(dev)
+        B = systec.quantize_bf16(B32) if a.form == "bf16" else B32
+        C = torch.empty((I, R), dtype=torch.float32, device=dev)
+        hist, eff = systec.expansion_stats(idx, I)
+        sb = 2 if a.form == "bf16" else 4
+        # compulsory bytes with a pointer over the leading index (the leading
+        # index need not be streamed): pointer + other indices + values +
+        # factor read once + output written once
+        b_alg = 4 * (I + 1) + nnz * (4 * (order - 1) + 4) + I * R * sb + 4 * I * R
+        step = lambda: systec.mttkrp(idx, val, B, out=C)  # noqa: E731
+        kernel_key, kernel_src = f"mttkrp{order}", ("mttkrp.hip",)
+        cfg = {"workload": a.workload, "order": order, "I": I, "R": R, "stored_nnz": nnz,
+               "effective_nnz": eff, "pattern_hist": hist, "B_storage": a.form,
+               "accumulate": "f32"}
+
+    if a.copy_calibration:
+        src = torch.empty(a.copy_calibration << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    # ---- timed region: K steps, synchronized on both sides ----
+    sec = timed(step, a.steps, a.warmup)
+    ms_step = sec * 1e3
+    out["value"] = eff / sec
+    out["ms_per_step"] = ms_step
+    cfg["canonical_nnz_per_s"] = cfg["stored_nnz"] / sec
+    cfg["B_alg_bytes"] = b_alg
+    out["config"] = cfg
+
+    # ---- dominant kernel: its own launches, HIP events on its stream ----
+    k_ms, launches = kernel_ms(step, max(10, a.steps))
+    achieved = b_alg / (k_ms * 1e-3) / 1e9
+    h = src_hash(*kernel_src)
+    traffic = load_traffic(f"{kernel_key}:{a.workload}:{a.form}", h, b_alg)
+    out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                       "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                       "traffic": traffic, "kernel": kernel_key, "kernel_ms": k_ms,
+                       "kernel_source_hash": h}
+
+    # ---- the non-symmetric comparison kernel on the expanded operand ----
+    if not a.no_compare:
+        try:
+            if a.workload.startswith("ssymv"):
+                frp, fcol, fval = systec.expand_csr(rp, col, val)
+                yf = torch.empty_like(y)
+                cstep = lambda: systec.spmv_csr(frp, fcol, fval, x, out=yf)  # noqa: E731
+            else:
+                fidx, fval = systec.expand_coo(idx, val, I)
+                Cf = torch.empty_like(C)
+                cstep = lambda: systec.mttkrp_full(fidx, fval, B, out=Cf)  # noqa: E731
+            csec = timed(cstep, a.steps, a.warmup)
+            out["nonsymmetric"] = {"ms_per_step": csec * 1e3, "effective_nnz_per_s": eff / csec,
+                                   "speedup_symmetric": csec / sec}
+            del cstep
+        except Exception as e:  # report, do not hide
+            out["nonsymmetric"] = {"error": str(e)}
+
+    # ---- CPU oracle leg (rank 0, one core), and the error of the GPU result ----
+    if not a.no_cpu:
+        import oracle
+        torch.cuda.synchronize()
+        if a.workload.startswith("ssymv"):
+            step()
+            got = y.cpu().numpy().astype(np.float64)
+            xref = (x.to(torch.float64).cpu().numpy())
+            vref = w["val"].astype(np.float32).astype(np.float64)
+            reps, t_cpu = 0, 0.0
+            while t_cpu < a.cpu_seconds and reps < 20:
+                t0 = time.perf_counter()
+                want, _ = oracle.ssymv(n, w["rowptr"], w["col"], vref, xref)
+                t_cpu += time.perf_counter() - t0
+                reps += 1
+            sample = f"the whole workload, {reps} oracle call(s)"
+            work = eff * reps
+        else:
+            step()
+            got = C.cpu().numpy().astype(np.float64)
+            Bref = B.to(torch.float64).cpu().numpy()
+            vref = w["val"].astype(np.float32).astype(np.float64)
+            # bounded sample: the first k stored entries (all of their expanded
+            # updates), sized to about cpu_seconds of oracle work
+            k = min(nnz, 200_000)
+            t0 = time.perf_counter()
+            oracle.mttkrp(order, I, w["idx"][:, :k].T, vref[:k], Bref)
+            t1 = time.perf_counter() - t0
+            k = int(min(nnz, max(k, k * a.cpu_seconds / max(t1, 1e-3))))
+            t0 = time.perf_counter()
+            _, cnt = oracle.mttkrp(order, I, w["idx"][:, :k].T, vref[:k], Bref)
+            t_cpu = time.perf_counter() - t0
+            work = cnt["effective_nnz"]
+            sample = f"first {k} of {nnz} stored entries ({work} expanded)"
+            # error on sampled output rows (full oracle restricted to them)
+            rng = np.random.Generator(np.random.PCG64(0))
+            rows_s = np.unique(rng.integers(0, I, 256))
+            mask = np.zeros(I, np.uint8)
+            mask[rows_s] = 1
+            want_full, _ = oracle.mttkrp(order, I, w["idx"].T, vref, Bref, row_mask=mask)
+            got, want = got[rows_s], want_full[rows_s]
+        err = float(np.linalg.norm(got - want) / max(np.linalg.norm(want), 1e-300))
+        out["cpu_baseline"] = {"value": work / t_cpu, "unit": "effective nnz/s", "cores": 1,
+                               "kind": "oracle", "sample": sample,
+                               "host_cpu": _cpu_model(), "host_nproc": os.cpu_count()}
+        out["oracle_rel_err"] = err
+    out["setup_s"] = {"generate": round(t_gen, 2)}
+    print(json.dumps(out), flush=True)
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+if __name__ == "__main__":
+    main()

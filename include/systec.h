@@ -1,0 +1,230 @@
+/*
+ * systec.h - symmetric sparse tensor kernels on AMD Instinct MI355X (gfx950).
+ *
+ * The library evaluates kernels whose sparse operand is a fully symmetric
+ * tensor stored by its canonical coordinates only (indices ascending, the
+ * upper triangle for a matrix; SySTeC, arXiv 2406.09266, Sec. 2.1,
+ * definitions "Symmetry" and "Canonical"). Each stored entry is expanded on
+ * the fly into its distinct index permutations: one read of a stored value
+ * serves every output it contributes to (Sec. 3.1, "reusing canonical
+ * reads"), weighted by how many distinct permutations land on the same output
+ * (Sec. 3.2.2, invisible output symmetry; Sec. 4.2.5 and 4.2.7). The result is
+ * the plain kernel over the full symmetric tensor.
+ *
+ * Conventions for every entry point:
+ *  - Return value: SYSTEC_OK (0) or a systec_status code. Nothing throws or
+ *    aborts across this interface. systec_last_error() gives a message for
+ *    the last failure on the calling thread.
+ *  - Indices are 0-based int32. Counts are int64 but must stay below 2^31.
+ *  - Pointers marked "device" address GPU memory (hipMalloc, torch CUDA
+ *    tensors); "host" pointers address CPU memory. The caller owns every
+ *    buffer it passes. Calls are asynchronous on `stream` (a hipStream_t;
+ *    NULL is the default stream): buffers must stay valid until the stream's
+ *    work completes. Output buffers are overwritten (the library zeroes them
+ *    on `stream`); there is no accumulate mode.
+ *  - Arguments are checked on the host: a bad size, order, dtype or NULL
+ *    pointer (other than for empty inputs) returns SYSTEC_EINVAL and launches
+ *    nothing. The canonical form of the sparse operand is the caller's
+ *    contract; systec_validate_* checks it on the device and
+ *    systec_canonicalize_coo establishes it on the host. A HIP failure
+ *    returns SYSTEC_EDEVICE with HIP's message.
+ *  - Floating point: stored tensor values are FP32. Vectors and factor
+ *    matrices are FP32 or BF16 (systec_dtype); BF16 values are widened
+ *    exactly to FP32 in registers. Products and sums are FP32; outputs are
+ *    accumulated with FP32 atomics, so their summation order (and last bits)
+ *    varies between runs. Scalar results are reduced in FP64 at the end.
+ */
+#ifndef SYSTEC_H
+#define SYSTEC_H
+
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define SYSTEC_API __attribute__((visibility("default")))
+#else
+#define SYSTEC_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SYSTEC_OK = 0,
+  SYSTEC_EINVAL = 1,     /* bad argument (size, order, dtype, NULL pointer)   */
+  SYSTEC_ENONCANON = 2,  /* sparse operand not in canonical form (validation) */
+  SYSTEC_ENOMEM = 3,     /* device allocation failed                          */
+  SYSTEC_EBUDGET = 4,    /* request can never fit the serving memory budget   */
+  SYSTEC_EBUSY = 5,      /* serving queue full                                */
+  SYSTEC_ETIMEOUT = 6,   /* wait timed out                                    */
+  SYSTEC_ENOTFOUND = 7,  /* unknown tensor or request id                      */
+  SYSTEC_EDEVICE = 8     /* HIP runtime or kernel launch failure              */
+} systec_status;
+
+/* Element type of a dense vector or factor matrix. */
+typedef enum { SYSTEC_F32 = 0, SYSTEC_BF16 = 1 } systec_dtype;
+
+/* A hipStream_t passed as an opaque pointer (torch: current_stream().cuda_stream). */
+typedef void* systec_stream;
+
+/* Message for the last failing call on this thread ("" if none). Never NULL. */
+SYSTEC_API const char* systec_last_error(void);
+
+/* Library version string. */
+SYSTEC_API const char* systec_version(void);
+
+/* ------------------------------------------------------------------------
+ * SSYMV  y = A x  (Sec. 5.2.1: A symmetric sparse, x and y dense).
+ *
+ * A is given by its stored upper triangle in CSR (diagonal included):
+ *   rowptr  device int32[n+1], rowptr[0] = 0, nondecreasing, rowptr[n] = nnz
+ *   col     device int32[nnz], col >= row, ascending within a row, < n
+ *   val     device float[nnz]
+ * A stored off-diagonal a = A[i,j] (i < j) updates y[i] += a x[j] and
+ * y[j] += a x[i]; a diagonal one updates y[i] += a x[i] (Sec. 3.1, the SSYMV
+ * figure). The stored value of a diagonal entry is not pre-scaled.
+ *   x       device, n elements of dtype xdt (F32 or BF16)
+ *   y       device float[n], overwritten.
+ * n >= 1, 0 <= nnz < 2^31. Errors: EINVAL, EDEVICE.
+ * ---------------------------------------------------------------------- */
+SYSTEC_API int systec_ssymv(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col,
+                 const float* val, const void* x, systec_dtype xdt, float* y,
+                 systec_stream stream);
+
+/* ------------------------------------------------------------------------
+ * SYPRD  s = x^T A x  (Sec. 5.2.3; Sec. 3.2.2: an off-diagonal stored entry
+ * contributes 2 x[i] a x[j], a diagonal one x[i] a x[i]).
+ * A, x as for systec_ssymv. Per-block partial sums are FP32; the final sum
+ * over blocks is FP64 on the device.
+ *   out     device double[1], overwritten.
+ * Errors: EINVAL, EDEVICE.
+ * ---------------------------------------------------------------------- */
+SYSTEC_API int systec_syprd(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col,
+                 const float* val, const void* x, systec_dtype xdt, double* out,
+                 systec_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Symmetric MTTKRP of order N = 3, 4, 5 (Sec. 5.2.6):
+ *   C[i,r] = sum_{k2..kN} T[i,k2,..,kN] * B[k2,r] * ... * B[kN,r]
+ * T is fully symmetric, given by its canonical entries in COO, structure of
+ * arrays, sorted lexicographically (so grouped by the leading index):
+ *   idx     host array of `order` device pointers; idx[t] is int32[nnz] and
+ *           idx[0][e] <= idx[1][e] <= ... <= idx[order-1][e] < I
+ *   val     device float[nnz]
+ *   B       device I x R row-major, dtype bdt (F32 or BF16)
+ *   C       device float I x R row-major, overwritten.
+ * Each entry with value v updates, for every slot t that starts a run of
+ * equal indices, C[idx[t][e], :] += coef * v * prod_{s != t} B[idx[s][e], :],
+ * where coef = (number of distinct permutations of the tuple) * (run
+ * length) / order. (Sec. 3.1: N!/m! assignments per read; Sec. 4.3, the 3-D
+ * derivation and its split loop nests.)
+ * order in {3,4,5}, I >= 1, R >= 1, 0 <= nnz < 2^31, I*R < 2^31.
+ * Errors: EINVAL, EDEVICE.
+ * ---------------------------------------------------------------------- */
+SYSTEC_API int systec_mttkrp(int order, int64_t I, int64_t nnz, const int32_t* const* idx,
+                  const float* val, const void* B, systec_dtype bdt, int64_t R, float* C,
+                  systec_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Comparison kernels without symmetry (the paper's baseline is the same
+ * kernel over the full tensor; Sec. 5.2, results normalized to it).
+ *
+ * systec_spmv_csr: y = A x for a general CSR matrix (full, not a triangle);
+ *   arguments as for systec_ssymv without the col >= row condition.
+ * systec_mttkrp_full: C[i,:] = sum over the listed (not symmetric) entries
+ *   of v * prod_{t>=1} B[idx[t][e], :], output row idx[0][e]. idx[0] must be
+ *   nondecreasing (grouped by output row); other slots are unconstrained.
+ * ---------------------------------------------------------------------- */
+SYSTEC_API int systec_spmv_csr(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col,
+                    const float* val, const void* x, systec_dtype xdt, float* y,
+                    systec_stream stream);
+SYSTEC_API int systec_mttkrp_full(int order, int64_t I, int64_t nnz, const int32_t* const* idx,
+                       const float* val, const void* B, systec_dtype bdt, int64_t R, float* C,
+                       systec_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Expansion into the full (non-symmetric) tensor, for the comparison
+ * kernels. Setup work, not part of a timed kernel.
+ *
+ * systec_expand_csr_size / systec_expand_csr: from the stored upper triangle
+ *   (as for systec_ssymv) build the full CSR of A = U + U^T - diag(U).
+ *   *full_nnz (host) receives 2*nnz - (number of diagonal entries). The
+ *   caller allocates full_rowptr int32[n+1], full_col int32[full_nnz],
+ *   full_val float[full_nnz] (device). Columns within a row are in no
+ *   particular order. Synchronizes `stream`.
+ * systec_expand_coo_size / systec_expand_coo: from canonical COO (as for
+ *   systec_mttkrp) write every distinct permutation of every entry, grouped
+ *   by the first index (rows ascending; order within a row unspecified).
+ *   *full_nnz (host) receives the number of expanded entries. out_idx is a
+ *   host array of `order` device int32[full_nnz] pointers; out_val device
+ *   float[full_nnz]. Synchronizes `stream`.
+ * ---------------------------------------------------------------------- */
+SYSTEC_API int systec_expand_csr_size(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col,
+                           int64_t* full_nnz, systec_stream stream);
+SYSTEC_API int systec_expand_csr(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col,
+                      const float* val, int32_t* full_rowptr, int32_t* full_col,
+                      float* full_val, systec_stream stream);
+SYSTEC_API int systec_expand_coo_size(int order, int64_t I, int64_t nnz, const int32_t* const* idx,
+                           int64_t* full_nnz, systec_stream stream);
+SYSTEC_API int systec_expand_coo(int order, int64_t I, int64_t nnz, const int32_t* const* idx,
+                      const float* val, int32_t* const* out_idx, float* out_val,
+                      systec_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Expansion statistics (integer, exact): for canonical COO (order 2..5),
+ * hist[m] (host int64[16]) receives the number of entries whose sorted tuple
+ * has equality pattern m (bit t set when idx[t] == idx[t+1]);
+ * *effective_nnz (host) receives the sum over entries of the number of
+ * distinct permutations. Synchronizes `stream`.
+ * For order 2, pass the row index of every entry in idx[0] and the column
+ * in idx[1]. Errors: EINVAL, EDEVICE.
+ * ---------------------------------------------------------------------- */
+SYSTEC_API int systec_expansion_stats(int order, int64_t I, int64_t nnz, const int32_t* const* idx,
+                           int64_t* hist, int64_t* effective_nnz, systec_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Validation of the canonical form on the device. Returns SYSTEC_OK if it
+ * holds, SYSTEC_ENONCANON (with a message naming the first kind of
+ * violation found) if not. Synchronizes `stream`.
+ * systec_validate_csr_upper: rowptr as documented, 0 <= col < n, col >= row,
+ *   columns strictly ascending within each row.
+ * systec_validate_coo: indices < I, each tuple ascending, the list strictly
+ *   increasing in lexicographic order (sorted, no duplicate tuples).
+ * ---------------------------------------------------------------------- */
+SYSTEC_API int systec_validate_csr_upper(int64_t n, int64_t nnz, const int32_t* rowptr,
+                              const int32_t* col, systec_stream stream);
+SYSTEC_API int systec_validate_coo(int order, int64_t I, int64_t nnz, const int32_t* const* idx,
+                        systec_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Host helper: brings a COO list (host memory, structure of arrays, any
+ * order) into canonical form in place: sorts each tuple, sorts the list
+ * lexicographically and sums duplicate tuples. *nnz_out receives the new
+ * length (entries beyond it are unspecified). val is host double.
+ * ---------------------------------------------------------------------- */
+SYSTEC_API int systec_canonicalize_coo(int order, int64_t nnz, int32_t* const* idx, double* val,
+                            int64_t* nnz_out);
+
+/* ------------------------------------------------------------------------
+ * Quantization of FP32 to BF16 with round-to-nearest-even, on the device
+ * (the served precision form stores vectors and factors in BF16).
+ *   in device float[n], out device uint16[n] (BF16 bit patterns).
+ * ---------------------------------------------------------------------- */
+SYSTEC_API int systec_quantize_bf16(const float* in, uint16_t* out, int64_t n, systec_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Kernel timing. When enabled, the library records a pair of HIP events
+ * around every launch of a hot kernel (SSYMV, SYPRD, MTTKRP and the
+ * comparison kernels) on the stream it is launched on.
+ * systec_kernel_timing_read synchronizes those events and returns the
+ * summed duration (milliseconds) and the number of launches timed since the
+ * last read, then resets both. Not thread-safe with concurrent launches.
+ * ---------------------------------------------------------------------- */
+SYSTEC_API int systec_kernel_timing(int enable);
+SYSTEC_API int systec_kernel_timing_read(double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SYSTEC_H */

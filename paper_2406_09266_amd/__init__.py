@@ -1,0 +1,254 @@
+"""Symmetric sparse tensor kernels on AMD Instinct MI355X (gfx950).
+
+A thin Python binding over the C ABI of libsystec.so (include/systec.h).
+Torch tensors supply device memory and the current HIP stream; the binding
+only marshals arguments. Every step of the computation runs in the library's
+HIP kernels; nothing here computes.
+
+    import paper_2406_09266_amd as systec
+    y = systec.ssymv(rowptr, col, val, x)          # y = A x, A symmetric (upper CSR)
+    s = systec.syprd(rowptr, col, val, x)          # x^T A x (FP64 device scalar)
+    C = systec.mttkrp([i1, i2, i3], val, B)        # symmetric MTTKRP, order 3..5
+
+Symmetric operands are given by their canonical entries (ascending indices,
+the upper triangle for a matrix), as in SySTeC (arXiv 2406.09266, Sec. 2.1).
+"""
+from __future__ import annotations
+
+import ctypes
+
+from . import _lib
+from ._lib import SYSTEC_BF16, SYSTEC_F32, SystecError, call, ptr_array
+
+__all__ = [
+    "SystecError", "ssymv", "syprd", "mttkrp", "spmv_csr", "mttkrp_full", "expand_csr",
+    "expand_coo", "expansion_stats", "validate_csr_upper", "validate_coo",
+    "canonicalize_coo", "quantize_bf16", "KernelTimer", "version",
+]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dtype_code(t):
+    torch = _torch()
+    if t.dtype == torch.float32:
+        return SYSTEC_F32
+    if t.dtype == torch.bfloat16:
+        return SYSTEC_BF16
+    raise TypeError(f"vector/factor dtype must be float32 or bfloat16, got {t.dtype}")
+
+
+def _dev(t, dtype=None, name="tensor"):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _p(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def version():
+    return _lib.lib().systec_version().decode()
+
+
+# ---------------------------------------------------------------- SSYMV ----
+
+def ssymv(rowptr, col, val, x, out=None, stream=None):
+    """y = A x, A symmetric given by its upper-triangle CSR (int32 rowptr/col,
+    float32 val). x is float32 or bfloat16; y is float32."""
+    torch = _torch()
+    n = rowptr.numel() - 1
+    _dev(rowptr, torch.int32, "rowptr"), _dev(col, torch.int32, "col")
+    _dev(val, torch.float32, "val"), _dev(x, None, "x")
+    if x.numel() != n:
+        raise ValueError("x must have n elements")
+    y = out if out is not None else torch.empty(n, dtype=torch.float32, device=x.device)
+    _dev(y, torch.float32, "out")
+    call("systec_ssymv", n, col.numel(), _p(rowptr), _p(col), _p(val), _p(x), _dtype_code(x),
+         _p(y), _stream(stream))
+    return y
+
+
+def spmv_csr(rowptr, col, val, x, out=None, stream=None):
+    """y = A x for a general (full) CSR matrix: the comparison kernel."""
+    torch = _torch()
+    n = rowptr.numel() - 1
+    y = out if out is not None else torch.empty(n, dtype=torch.float32, device=x.device)
+    call("systec_spmv_csr", n, col.numel(), _p(rowptr), _p(col), _p(val), _p(x),
+         _dtype_code(x), _p(y), _stream(stream))
+    return y
+
+
+def syprd(rowptr, col, val, x, out=None, stream=None):
+    """x^T A x (A symmetric, upper-triangle CSR) as a float64 device scalar."""
+    torch = _torch()
+    n = rowptr.numel() - 1
+    s = out if out is not None else torch.empty(1, dtype=torch.float64, device=x.device)
+    call("systec_syprd", n, col.numel(), _p(rowptr), _p(col), _p(val), _p(x), _dtype_code(x),
+         _p(s), _stream(stream))
+    return s
+
+
+# --------------------------------------------------------------- MTTKRP ----
+
+def _idx_ptrs(idx, name="idx"):
+    torch = _torch()
+    for t in idx:
+        _dev(t, torch.int32, name)
+    return ptr_array([t.data_ptr() for t in idx])
+
+
+def mttkrp(idx, val, B, out=None, stream=None):
+    """Symmetric MTTKRP: idx is a list of `order` (3..5) int32 index tensors of
+    canonical COO (each tuple ascending, list sorted), val float32, B (I x R)
+    float32 or bfloat16. Returns C (I x R) float32."""
+    torch = _torch()
+    order = len(idx)
+    I, R = B.shape
+    _dev(B, None, "B"), _dev(val, torch.float32, "val")
+    C = out if out is not None else torch.empty((I, R), dtype=torch.float32, device=B.device)
+    pp, keep = _idx_ptrs(idx)
+    call("systec_mttkrp", order, I, val.numel(), pp, _p(val), _p(B), _dtype_code(B), R, _p(C),
+         _stream(stream))
+    del keep
+    return C
+
+
+def mttkrp_full(idx, val, B, out=None, stream=None):
+    """MTTKRP over listed (non-symmetric) entries grouped by idx[0]: the
+    comparison kernel over an expanded tensor."""
+    torch = _torch()
+    order = len(idx)
+    I, R = B.shape
+    C = out if out is not None else torch.empty((I, R), dtype=torch.float32, device=B.device)
+    pp, keep = _idx_ptrs(idx)
+    call("systec_mttkrp_full", order, I, val.numel(), pp, _p(val), _p(B), _dtype_code(B), R,
+         _p(C), _stream(stream))
+    del keep
+    return C
+
+
+# ------------------------------------------------------------ expansion ----
+
+def expand_csr(rowptr, col, val, stream=None):
+    """Full CSR of A = U + U^T - diag(U) (setup for the comparison kernel)."""
+    torch = _torch()
+    n = rowptr.numel() - 1
+    full = ctypes.c_int64()
+    call("systec_expand_csr_size", n, col.numel(), _p(rowptr), _p(col), ctypes.byref(full),
+         _stream(stream))
+    frp = torch.empty(n + 1, dtype=torch.int32, device=rowptr.device)
+    fcol = torch.empty(max(1, full.value), dtype=torch.int32, device=rowptr.device)
+    fval = torch.empty(max(1, full.value), dtype=torch.float32, device=rowptr.device)
+    call("systec_expand_csr", n, col.numel(), _p(rowptr), _p(col), _p(val), _p(frp), _p(fcol),
+         _p(fval), _stream(stream))
+    return frp, fcol[: full.value], fval[: full.value]
+
+
+def expand_coo(idx, val, I, stream=None):
+    """Every distinct permutation of every canonical entry, grouped by the
+    first index (setup for the comparison kernel)."""
+    torch = _torch()
+    order = len(idx)
+    pp, keep = _idx_ptrs(idx)
+    full = ctypes.c_int64()
+    call("systec_expand_coo_size", order, I, val.numel(), pp, ctypes.byref(full), _stream(stream))
+    dev = val.device
+    out = [torch.empty(max(1, full.value), dtype=torch.int32, device=dev) for _ in range(order)]
+    oval = torch.empty(max(1, full.value), dtype=torch.float32, device=dev)
+    op, okeep = ptr_array([t.data_ptr() for t in out])
+    call("systec_expand_coo", order, I, val.numel(), pp, _p(val), op, _p(oval), _stream(stream))
+    del keep, okeep
+    return [t[: full.value] for t in out], oval[: full.value]
+
+
+def expansion_stats(idx, I, stream=None):
+    """(hist over equality patterns, effective nnz) computed on the device."""
+    order = len(idx)
+    pp, keep = _idx_ptrs(idx)
+    hist = (ctypes.c_int64 * 16)()
+    eff = ctypes.c_int64()
+    n = idx[0].numel()
+    call("systec_expansion_stats", order, I, n, pp, ctypes.cast(hist, _lib.PI64),
+         ctypes.byref(eff), _stream(stream))
+    del keep
+    return [int(hist[m]) for m in range(1 << (order - 1))], int(eff.value)
+
+
+# ----------------------------------------------------------- validation ----
+
+def validate_csr_upper(rowptr, col, stream=None):
+    """Raises SystecError (SYSTEC_ENONCANON) unless the CSR is a canonical upper triangle."""
+    call("systec_validate_csr_upper", rowptr.numel() - 1, col.numel(), _p(rowptr), _p(col),
+         _stream(stream))
+
+
+def validate_coo(idx, I, stream=None):
+    """Raises SystecError (SYSTEC_ENONCANON) unless the COO is canonical."""
+    pp, keep = _idx_ptrs(idx)
+    call("systec_validate_coo", len(idx), I, idx[0].numel(), pp, _stream(stream))
+    del keep
+
+
+def canonicalize_coo(idx, val):
+    """Host helper: sort each tuple, sort the list, sum duplicates (numpy
+    int32 index arrays and a float64 value array, modified in place).
+    Returns the new length."""
+    import numpy as np
+    order = len(idx)
+    for a in idx:
+        if a.dtype != np.int32 or not a.flags.c_contiguous:
+            raise TypeError("index arrays must be contiguous int32")
+    if val.dtype != np.float64 or not val.flags.c_contiguous:
+        raise TypeError("val must be contiguous float64")
+    pp, keep = ptr_array([a.ctypes.data for a in idx])
+    out = ctypes.c_int64()
+    call("systec_canonicalize_coo", order, val.size, pp, ctypes.c_void_p(val.ctypes.data),
+         ctypes.byref(out))
+    del keep
+    return int(out.value)
+
+
+def quantize_bf16(x, out=None, stream=None):
+    """FP32 -> BF16 (round to nearest even) on the device."""
+    torch = _torch()
+    _dev(x, torch.float32, "x")
+    y = out if out is not None else torch.empty(x.shape, dtype=torch.bfloat16, device=x.device)
+    call("systec_quantize_bf16", _p(x), _p(y), x.numel(), _stream(stream))
+    return y
+
+
+class KernelTimer:
+    """Times the library's hot-kernel launches with HIP events on their own
+    stream:  with KernelTimer() as kt: ...;  kt.total_ms, kt.launches."""
+
+    def __enter__(self):
+        call("systec_kernel_timing", 1)
+        self.read()  # discard anything recorded before
+        return self
+
+    def read(self):
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        call("systec_kernel_timing_read", ctypes.byref(ms), ctypes.byref(n))
+        return ms.value, n.value
+
+    def __exit__(self, *exc):
+        self.total_ms, self.launches = self.read()
+        call("systec_kernel_timing", 0)
+        return False

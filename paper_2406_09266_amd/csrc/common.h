@@ -1,0 +1,121 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "systec.h"
+
+namespace systec {
+
+// ---- error reporting (abi.cpp) -------------------------------------------
+int fail(int status, const std::string& msg);
+int check_hip(hipError_t e, const char* what);
+// Checks the launch that was just issued; records an error message on failure.
+int check_launch(const char* what);
+
+// ---- kernel timing (abi.cpp) ---------------------------------------------
+// Brackets one hot-kernel launch with events when timing is enabled.
+struct LaunchTimer {
+  explicit LaunchTimer(hipStream_t s);
+  ~LaunchTimer();
+  hipStream_t stream;
+  hipEvent_t start = nullptr;
+};
+
+// ---- device helpers --------------------------------------------------------
+constexpr int kWave = 64;
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t b) {
+  return __uint_as_float(static_cast<uint32_t>(b) << 16);  // exact widening
+}
+
+template <typename T>
+__device__ __forceinline__ float load_f32(const T* p, int64_t i);
+template <>
+__device__ __forceinline__ float load_f32<float>(const float* p, int64_t i) {
+  return p[i];
+}
+template <>
+__device__ __forceinline__ float load_f32<uint16_t>(const uint16_t* p, int64_t i) {
+  return bf16_to_f32(p[i]);
+}
+
+// FP32 atomic add whose result is unused (hardware global_atomic_add_f32).
+__device__ __forceinline__ void atomic_add_noret(float* p, float v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---- launchers (one per hot kernel family) ---------------------------------
+// All sizes are validated by the caller (abi.cpp).
+int launch_fill_f32(float* p, int64_t n, hipStream_t s);
+int launch_ssymv(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col,
+                 const float* val, const void* x, systec_dtype xdt, float* y, bool symmetric,
+                 hipStream_t s);
+int launch_syprd(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col,
+                 const float* val, const void* x, systec_dtype xdt, double* out,
+                 hipStream_t s);
+int launch_mttkrp(int order, int64_t I, int64_t nnz, const int32_t* const* idx,
+                  const float* val, const void* B, systec_dtype bdt, int64_t R, float* C,
+                  bool symmetric, hipStream_t s);
+int launch_quantize_bf16(const float* in, uint16_t* out, int64_t n, hipStream_t s);
+int launch_expansion_stats(int order, int64_t nnz, const int32_t* const* idx,
+                           unsigned long long* d_counts /* 17 */, hipStream_t s);
+int launch_validate_csr_upper(int64_t n, int64_t nnz, const int32_t* rowptr,
+                              const int32_t* col, unsigned int* d_flags, hipStream_t s);
+int launch_validate_coo(int order, int64_t I, int64_t nnz, const int32_t* const* idx,
+                        unsigned int* d_flags, hipStream_t s);
+int expand_csr_size(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col,
+                    int64_t* full_nnz, hipStream_t s);
+int expand_csr(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col,
+               const float* val, int32_t* full_rowptr, int32_t* full_col, float* full_val,
+               hipStream_t s);
+int expand_coo_size(int order, int64_t I, int64_t nnz, const int32_t* const* idx,
+                    int64_t* full_nnz, hipStream_t s);
+int expand_coo(int order, int64_t I, int64_t nnz, const int32_t* const* idx, const float* val,
+               int32_t* const* out_idx, float* out_val, hipStream_t s);
+
+// ---- multiplicity rule (host and device) ----------------------------------
+// For a sorted tuple of `order` indices whose equality pattern is `mask`
+// (bit t set when c[t] == c[t+1]) the number of distinct permutations is
+// order! / prod(run length!). Slot t that starts a run of length m gets the
+// coefficient (distinct permutations) * m / order, the number of permutations
+// that put that run's value in the output slot; other slots get 0.
+struct CoefTable {
+  float coef[16][5];
+  int32_t mult[16];
+};
+
+constexpr int64_t cfact(int n) { return n <= 1 ? 1 : n * cfact(n - 1); }
+
+constexpr CoefTable make_coef_table(int order) {
+  CoefTable t{};
+  for (int mask = 0; mask < 16; ++mask) {
+    for (int s = 0; s < 5; ++s) t.coef[mask][s] = 0.0f;
+    t.mult[mask] = 0;
+    if (mask >= (1 << (order - 1))) continue;
+    int run_len[5] = {0, 0, 0, 0, 0};
+    int run_start[5] = {0, 0, 0, 0, 0};
+    int runs = 0;
+    for (int s = 0; s < order; ++s) {
+      bool continues = s > 0 && ((mask >> (s - 1)) & 1);
+      if (!continues) {
+        run_start[runs] = s;
+        run_len[runs] = 0;
+        ++runs;
+      }
+      ++run_len[runs - 1];
+    }
+    int64_t denom = 1;
+    for (int r = 0; r < runs; ++r) denom *= cfact(run_len[r]);
+    int64_t mult = cfact(order) / denom;
+    t.mult[mask] = static_cast<int32_t>(mult);
+    for (int r = 0; r < runs; ++r)
+      t.coef[mask][run_start[r]] = static_cast<float>(mult * run_len[r] / order);
+  }
+  return t;
+}
+
+}  // namespace systec

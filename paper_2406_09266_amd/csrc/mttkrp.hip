@@ -1,0 +1,186 @@
+// Symmetric MTTKRP of order N = 3, 4, 5 over canonical COO, and the plain
+// MTTKRP over an expanded (non-symmetric) COO used as the comparison.
+//
+// Method (SySTeC, arXiv 2406.09266, Sec. 4.3 and 5.2.6): a stored entry
+// (c1 <= ... <= cN, v) stands for v at every distinct permutation of its
+// indices. For MTTKRP the permutations that put the same index value in the
+// output slot produce identical updates (invisible output symmetry,
+// Sec. 3.2.2), so they are merged into one update scaled by their count
+// (distributive grouping, Sec. 4.2.7). The count depends only on the
+// equality pattern of the sorted tuple, so it comes from a small table
+// indexed by that pattern (the simplicial lookup table, Sec. 4.2.5):
+//   C[c_t, :] += coef[pattern][t] * v * prod_{s != t} B[c_s, :]
+// for each slot t that starts a run of equal indices. Each factor row is
+// read once per entry (common tensor access elimination, Sec. 4.2.1).
+//
+// GPU decomposition. A wavefront owns a tile of consecutive entries. It is
+// split into groups of L lanes (L = 8/16/32/64, the smallest power of two
+// >= R, or 64 with column blocks for R > 64); each group walks every
+// (64/L)-th entry of the tile with one lane per output column, so factor-row
+// gathers and output-row updates are contiguous L-wide accesses. Entries are
+// sorted by c1, so slot 1 accumulates in registers across a run of equal c1
+// and is written once per run (the workspace transformation, Sec. 4.2.8);
+// the other run-start slots scatter with FP32 atomics.
+#include "common.h"
+
+namespace systec {
+
+__constant__ CoefTable kCoef3 = make_coef_table(3);
+__constant__ CoefTable kCoef4 = make_coef_table(4);
+__constant__ CoefTable kCoef5 = make_coef_table(5);
+
+namespace {
+
+constexpr int kWaves = 4;
+constexpr int kBlock = kWave * kWaves;
+constexpr int kTileE = 256;  // entries per wavefront tile
+
+struct IdxPtrs {
+  const int32_t* p[5];
+};
+
+template <int N>
+__device__ __forceinline__ const CoefTable& coef_table();
+template <>
+__device__ __forceinline__ const CoefTable& coef_table<3>() { return kCoef3; }
+template <>
+__device__ __forceinline__ const CoefTable& coef_table<4>() { return kCoef4; }
+template <>
+__device__ __forceinline__ const CoefTable& coef_table<5>() { return kCoef5; }
+
+// Leave-one-out products: loo[t] = prod_{s != t} b[s].
+template <int N>
+__device__ __forceinline__ void leave_one_out(const float (&b)[N], float (&loo)[N]) {
+  float pre[N], suf[N];
+  pre[0] = 1.0f;
+#pragma unroll
+  for (int t = 1; t < N; ++t) pre[t] = (t == 1) ? b[0] : pre[t - 1] * b[t - 1];
+  suf[N - 1] = 1.0f;
+#pragma unroll
+  for (int t = N - 2; t >= 0; --t) suf[t] = (t == N - 2) ? b[N - 1] : suf[t + 1] * b[t + 1];
+#pragma unroll
+  for (int t = 0; t < N; ++t)
+    loo[t] = (t == 0) ? suf[0] : (t == N - 1) ? pre[N - 1] : pre[t] * suf[t];
+}
+
+// kSym: canonical entries of a symmetric tensor (coefficient table, every
+// run-start slot updated). Otherwise: plain entries, only slot 1 is output.
+template <int N, typename BT, int L, bool kSym>
+__global__ __launch_bounds__(kBlock) void mttkrp_tiles_kernel(int nnz, IdxPtrs idx,
+                                                            const float* __restrict__ val,
+                                                            const BT* __restrict__ B, int ldb,
+                                                            float* __restrict__ C, int ldc,
+                                                            int col0, int ncols) {
+  constexpr int G = kWave / L;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int g = lane / L;
+  const int cl = lane - g * L;
+  const bool col_ok = cl < ncols;
+  const int col = col0 + (col_ok ? cl : 0);
+  const int64_t wave = static_cast<int64_t>(blockIdx.x) * kWaves + threadIdx.x / kWave;
+  const int64_t e_begin = wave * kTileE;
+  if (e_begin >= nnz) return;
+  const int e_end = static_cast<int>(min<int64_t>(nnz, e_begin + kTileE));
+
+  int cur = -1;
+  float acc = 0.0f;
+  for (int e = static_cast<int>(e_begin) + g; e < e_end; e += G) {
+    int c[N];
+#pragma unroll
+    for (int t = 0; t < N; ++t) c[t] = idx.p[t][e];
+    const float v = val[e];
+    float b[N];
+#pragma unroll
+    for (int t = 0; t < N; ++t) b[t] = load_f32(B, static_cast<int64_t>(c[t]) * ldb + col);
+    float loo[N];
+    leave_one_out<N>(b, loo);
+
+    if (c[0] != cur) {
+      if (cur >= 0 && col_ok) atomic_add_noret(C + static_cast<int64_t>(cur) * ldc + col, acc);
+      cur = c[0];
+      acc = 0.0f;
+    }
+    if constexpr (kSym) {
+      int mask = 0;
+#pragma unroll
+      for (int t = 0; t + 1 < N; ++t) mask |= (c[t] == c[t + 1]) ? (1 << t) : 0;
+      const float* coef = coef_table<N>().coef[mask];
+      acc += coef[0] * v * loo[0];
+#pragma unroll
+      for (int t = 1; t < N; ++t) {
+        const float k = coef[t];
+        if (k != 0.0f && col_ok)
+          atomic_add_noret(C + static_cast<int64_t>(c[t]) * ldc + col, k * v * loo[t]);
+      }
+    } else {
+      acc += v * loo[0];
+    }
+  }
+  if (cur >= 0 && col_ok) atomic_add_noret(C + static_cast<int64_t>(cur) * ldc + col, acc);
+}
+
+template <int N, typename BT, int L, bool kSym>
+void launch_one(int nnz, const IdxPtrs& ip, const float* val, const BT* B, int ldb, float* C,
+                int ldc, int col0, int ncols, hipStream_t s) {
+  const int64_t tiles = (static_cast<int64_t>(nnz) + kTileE - 1) / kTileE;
+  const int64_t blocks = (tiles + kWaves - 1) / kWaves;
+  mttkrp_tiles_kernel<N, BT, L, kSym>
+      <<<dim3(blocks), dim3(kBlock), 0, s>>>(nnz, ip, val, B, ldb, C, ldc, col0, ncols);
+}
+
+template <int N, typename BT, bool kSym>
+void launch_cols(int nnz, const IdxPtrs& ip, const float* val, const BT* B, int R, float* C,
+                 hipStream_t s) {
+  if (R <= 8) {
+    launch_one<N, BT, 8, kSym>(nnz, ip, val, B, R, C, R, 0, R, s);
+  } else if (R <= 16) {
+    launch_one<N, BT, 16, kSym>(nnz, ip, val, B, R, C, R, 0, R, s);
+  } else if (R <= 32) {
+    launch_one<N, BT, 32, kSym>(nnz, ip, val, B, R, C, R, 0, R, s);
+  } else {
+    for (int c0 = 0; c0 < R; c0 += 64)
+      launch_one<N, BT, 64, kSym>(nnz, ip, val, B, R, C, R, c0, std::min(64, R - c0), s);
+  }
+}
+
+template <int N, bool kSym>
+void launch_order(int nnz, const IdxPtrs& ip, const float* val, const void* B, systec_dtype bdt,
+                  int R, float* C, hipStream_t s) {
+  if (bdt == SYSTEC_F32)
+    launch_cols<N, float, kSym>(nnz, ip, val, static_cast<const float*>(B), R, C, s);
+  else
+    launch_cols<N, uint16_t, kSym>(nnz, ip, val, static_cast<const uint16_t*>(B), R, C, s);
+}
+
+}  // namespace
+
+int launch_mttkrp(int order, int64_t I, int64_t nnz, const int32_t* const* idx,
+                  const float* val, const void* B, systec_dtype bdt, int64_t R, float* C,
+                  bool symmetric, hipStream_t s) {
+  int rc = launch_fill_f32(C, I * R, s);
+  if (rc != SYSTEC_OK || nnz == 0) return rc;
+  IdxPtrs ip{};
+  for (int t = 0; t < order; ++t) ip.p[t] = idx[t];
+  const int nz = static_cast<int>(nnz), r = static_cast<int>(R);
+  LaunchTimer timer(s);
+  switch (order) {
+    case 2:
+      if (!symmetric) launch_order<2, false>(nz, ip, val, B, bdt, r, C, s);
+      break;
+    case 3:
+      symmetric ? launch_order<3, true>(nz, ip, val, B, bdt, r, C, s)
+                : launch_order<3, false>(nz, ip, val, B, bdt, r, C, s);
+      break;
+    case 4:
+      symmetric ? launch_order<4, true>(nz, ip, val, B, bdt, r, C, s)
+                : launch_order<4, false>(nz, ip, val, B, bdt, r, C, s);
+      break;
+    default:
+      symmetric ? launch_order<5, true>(nz, ip, val, B, bdt, r, C, s)
+                : launch_order<5, false>(nz, ip, val, B, bdt, r, C, s);
+      break;
+  }
+  return check_launch(symmetric ? "mttkrp kernel" : "mttkrp (full) kernel");
+}
+
+}  // namespace systec

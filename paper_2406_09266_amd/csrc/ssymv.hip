@@ -1,0 +1,375 @@
+// SSYMV (y = A x) and SYPRD (s = x^T A x) over the stored upper triangle of a
+// symmetric sparse matrix, and the plain CSR SpMV used as the comparison.
+//
+// Method (SySTeC, arXiv 2406.09266): a stored entry a = A[i,j], i <= j, is
+// read once and serves both of its permutations: y[i] += a x[j] and, when
+// i < j, y[j] += a x[i] (Sec. 3.1, "reusing canonical reads"). The row-side
+// sums are accumulated in registers per row segment and written once per
+// segment (the workspace transformation of Sec. 4.2.8); the column-side
+// updates are scattered with FP32 atomics, which a parallel traversal of the
+// canonical triangle needs (Sec. 7, parallelization). SYPRD gives an
+// off-diagonal entry the factor 2 (Sec. 3.2.2, invisible output symmetry).
+//
+// GPU decomposition. The matrix is cut along its merge path (the row end
+// offsets and the entry indices as one sequence of n + nnz items) into tiles
+// of kTile = 512 items, so a wavefront's tile holds at most 512 entries and at
+// most 512 rows whatever the row lengths (long hub rows and long runs of
+// empty rows cost the same). The tile's entries are read with coalesced loads
+// (the index and value streams are read exactly once) and staged in LDS; lane
+// l then takes entries 8l .. 8l+7. The row of each entry comes from row-start
+// markers placed in LDS followed by a max-scan. Each lane sums its entries
+// sequentially by row; the wave combines the segments that cross lanes with a
+// DPP segmented scan, so a row spanning a whole tile costs one atomic.
+#include "common.h"
+
+namespace systec {
+namespace {
+
+constexpr int kV = 8;                 // entries per lane
+constexpr int kTile = kWave * kV;     // entries per wavefront tile
+constexpr int kWaves = 4;             // wavefronts per workgroup
+constexpr int kBlock = kWave * kWaves;
+
+// ---- wave-level primitives (DPP; wave64) ----------------------------------
+// DPP controls: row_shr:n = 0x110+n, row_bcast:15 = 0x142, row_bcast:31 = 0x143.
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ int dpp_i32(int old, int src) {
+  return __builtin_amdgcn_update_dpp(old, src, kCtrl, kRowMask, 0xf, false);
+}
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ float dpp_f32(float old, float src) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(src), kCtrl, kRowMask, 0xf,
+                                  false));
+}
+
+// Inclusive max-scan over the 64 lanes.
+__device__ __forceinline__ int wave_incl_max(int v) {
+  v = max(v, dpp_i32<0x111, 0xf>(INT_MIN, v));
+  v = max(v, dpp_i32<0x112, 0xf>(INT_MIN, v));
+  v = max(v, dpp_i32<0x114, 0xf>(INT_MIN, v));
+  v = max(v, dpp_i32<0x118, 0xf>(INT_MIN, v));
+  v = max(v, dpp_i32<0x142, 0xa>(INT_MIN, v));
+  v = max(v, dpp_i32<0x143, 0xc>(INT_MIN, v));
+  return v;
+}
+
+// Inclusive segmented sum over the 64 lanes; segments are runs of equal keys
+// (keys are nondecreasing across lanes).
+__device__ __forceinline__ float wave_seg_sum(int key, float v) {
+#define SYSTEC_SEG_STEP(CTRL, MASK)                         \
+  {                                                         \
+    const int k2 = dpp_i32<CTRL, MASK>(-2, key);            \
+    const float v2 = dpp_f32<CTRL, MASK>(0.0f, v);          \
+    v += (k2 == key) ? v2 : 0.0f;                           \
+  }
+  SYSTEC_SEG_STEP(0x111, 0xf)
+  SYSTEC_SEG_STEP(0x112, 0xf)
+  SYSTEC_SEG_STEP(0x114, 0xf)
+  SYSTEC_SEG_STEP(0x118, 0xf)
+  SYSTEC_SEG_STEP(0x142, 0xa)
+  SYSTEC_SEG_STEP(0x143, 0xc)
+#undef SYSTEC_SEG_STEP
+  return v;
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
+  return v;
+}
+
+// Merge-path split (Merrill & Garland's merge-based CSR decomposition): the
+// rows' end offsets and the entry indices form one sorted sequence of n + nnz
+// items; diagonal d of it splits at the largest row i in [0, n] with
+// rowptr[i] + i <= d. The wave searches cooperatively, 64 probes per step.
+__device__ __forceinline__ int merge_split(const int32_t* __restrict__ rowptr, int n,
+                                           int64_t d, int lane) {
+  int lo = 0, hi = n + 1;  // f(lo) <= d; hi == n+1 or f(hi) > d
+  while (hi - lo > 1) {
+    const int step = (hi - lo + kWave - 1) / kWave;
+    const int probe = lo + (lane + 1) * step;
+    const bool le = probe < hi && static_cast<int64_t>(rowptr[probe]) + probe <= d;
+    const int c = __popcll(__ballot(le));
+    const int nlo = lo + c * step;
+    hi = min(hi, lo + (c + 1) * step);
+    lo = nlo;
+  }
+  return lo;
+}
+
+// The entries of one merge-path tile, lane-contiguous: lane l holds tile
+// entries 8l .. 8l+7 (entries past the tile's end get val = 0 and the last
+// row).
+struct LaneEntries {
+  int row[kV];
+  int col[kV];
+  float val[kV];
+  int valid;  // number of valid entries of this lane (0..8)
+};
+
+// Per-wave LDS staging: row-start markers and the tile's columns and values.
+struct TileLds {
+  int head[kTile];
+  int col[kTile];
+  float val[kTile];
+};
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ void read8(const int* p, int (&o)[kV]) {
+  const int4 a = reinterpret_cast<const int4*>(p)[0], b = reinterpret_cast<const int4*>(p)[1];
+  o[0] = a.x; o[1] = a.y; o[2] = a.z; o[3] = a.w;
+  o[4] = b.x; o[5] = b.y; o[6] = b.z; o[7] = b.w;
+}
+
+// Loads merge-path tile `tile` (items [tile*kTile, (tile+1)*kTile) of the
+// n + nnz sequence): at most kTile rows and kTile entries. Returns false if
+// the tile holds no entry.
+__device__ __forceinline__ bool load_tile(const int32_t* __restrict__ rowptr,
+                                          const int32_t* __restrict__ col,
+                                          const float* __restrict__ val, int n, int nnz,
+                                          int64_t tile, int lane, TileLds& S, LaneEntries& L) {
+  const int64_t total = static_cast<int64_t>(n) + nnz;
+  const int64_t d0 = tile * kTile;
+  const int64_t d1 = min(d0 + kTile, total);
+  const int i0 = merge_split(rowptr, n, d0, lane);
+  const int i1 = merge_split(rowptr, n, d1, lane);
+  const int j0 = static_cast<int>(d0 - i0);
+  const int j1 = static_cast<int>(d1 - i1);
+  const int cnt = j1 - j0;  // 0..kTile
+  if (cnt <= 0) return false;
+
+  // row-start markers: head[p] = largest row whose first entry is j0 + p
+  {
+    int4* h4 = reinterpret_cast<int4*>(S.head + lane * kV);
+    const int4 none = make_int4(-1, -1, -1, -1);
+    h4[0] = none;
+    h4[1] = none;
+  }
+  wave_sync();
+  if (lane == 0) S.head[0] = i0;
+  wave_sync();
+  // rows (i0, i1] start at or after j0; at most kTile of them
+  for (int r = i0 + 1 + lane; r <= i1; r += kWave) {
+    const int s = rowptr[r];
+    if (s < j1) atomicMax(S.head + (s - j0), r);
+  }
+  // coalesced loads of the tile's entries into LDS
+#pragma unroll
+  for (int q = 0; q < kV; ++q) {
+    const int p = q * kWave + lane;
+    if (p < cnt) {
+      S.col[p] = col[j0 + p];
+      S.val[p] = val[j0 + p];
+    }
+  }
+  wave_sync();
+
+  int h[kV];
+  read8(S.head + lane * kV, h);
+#pragma unroll
+  for (int k = 1; k < kV; ++k) h[k] = max(h[k], h[k - 1]);
+  // carry-in: the largest marker of all earlier lanes
+  const int incl = wave_incl_max(h[kV - 1]);
+  int carry = __shfl_up(incl, 1);
+  if (lane == 0) carry = INT_MIN;
+#pragma unroll
+  for (int k = 0; k < kV; ++k) L.row[k] = max(h[k], carry);
+
+  L.valid = max(0, min(kV, cnt - lane * kV));
+  int c[kV];
+  read8(S.col + lane * kV, c);
+  const float* vp = S.val + lane * kV;
+  const float4 va = reinterpret_cast<const float4*>(vp)[0];
+  const float4 vb = reinterpret_cast<const float4*>(vp)[1];
+  const float v[kV] = {va.x, va.y, va.z, va.w, vb.x, vb.y, vb.z, vb.w};
+#pragma unroll
+  for (int k = 0; k < kV; ++k) {
+    const bool ok = k < L.valid;
+    L.col[k] = ok ? c[k] : L.row[k];
+    L.val[k] = ok ? v[k] : 0.0f;
+  }
+  return true;
+}
+
+// y (+)= A x over one tile. kSym: the stored entries are the upper triangle
+// and each off-diagonal entry also updates y[col].
+template <typename XT, bool kSym>
+__global__ __launch_bounds__(kBlock) void csr_tiles_kernel(int n, int nnz,
+                                                         const int32_t* __restrict__ rowptr,
+                                                         const int32_t* __restrict__ col,
+                                                         const float* __restrict__ val,
+                                                         const XT* __restrict__ x,
+                                                         float* __restrict__ y) {
+  __shared__ __attribute__((aligned(16))) TileLds s_tile[kWaves];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
+  const int64_t tile = static_cast<int64_t>(blockIdx.x) * kWaves + w;
+  if (tile * kTile >= static_cast<int64_t>(n) + nnz) return;  // wave-local sync only below
+  LaneEntries L;
+  if (!load_tile(rowptr, col, val, n, nnz, tile, lane, s_tile[w], L)) return;
+
+  // lane-sequential segmented sums; interior segments are flushed here
+  int first_key = L.row[0];
+  int cur = L.row[0];
+  float acc = 0.0f, head_val = 0.0f;
+  int nseg = 1;
+  float xr = load_f32(x, cur);
+#pragma unroll
+  for (int k = 0; k < kV; ++k) {
+    const int r = L.row[k];
+    if (r != cur) {
+      if (nseg == 1) head_val = acc;
+      else atomic_add_noret(y + cur, acc);
+      ++nseg;
+      cur = r;
+      acc = 0.0f;
+      if (kSym) xr = load_f32(x, cur);
+    }
+    if (k < L.valid) {
+      const int c = L.col[k];
+      const float a = L.val[k];
+      acc += a * load_f32(x, c);
+      if (kSym && c != r) atomic_add_noret(y + c, a * xr);
+    }
+  }
+  // segments that cross lanes
+  const int tail_key = cur;
+  const float tail = wave_seg_sum(tail_key, acc);
+  const int prev_key = __shfl_up(tail_key, 1);
+  const float prev_tail = __shfl_up(tail, 1);
+  const int next_first = __shfl_down(first_key, 1);
+  if (nseg >= 2) {
+    const float c = (lane > 0 && prev_key == first_key) ? prev_tail : 0.0f;
+    atomic_add_noret(y + first_key, head_val + c);
+  }
+  if (lane == kWave - 1 || next_first != tail_key) atomic_add_noret(y + tail_key, tail);
+}
+
+// SYPRD partial sums: one FP32 partial per workgroup.
+template <typename XT>
+__global__ __launch_bounds__(kBlock) void syprd_tiles_kernel(int n, int nnz,
+                                                           const int32_t* __restrict__ rowptr,
+                                                           const int32_t* __restrict__ col,
+                                                           const float* __restrict__ val,
+                                                           const XT* __restrict__ x,
+                                                           float* __restrict__ partial) {
+  __shared__ __attribute__((aligned(16))) TileLds s_tile[kWaves];
+  __shared__ float s_part[kWaves];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
+  const int64_t tile = static_cast<int64_t>(blockIdx.x) * kWaves + w;
+  float sum = 0.0f;
+  LaneEntries L;
+  if (tile * kTile < static_cast<int64_t>(n) + nnz &&
+      load_tile(rowptr, col, val, n, nnz, tile, lane, s_tile[w], L)) {
+#pragma unroll
+    for (int k = 0; k < kV; ++k) {
+      if (k < L.valid) {
+        const int r = L.row[k], c = L.col[k];
+        const float f = (r == c) ? 1.0f : 2.0f;
+        sum += f * L.val[k] * load_f32(x, r) * load_f32(x, c);
+      }
+    }
+  }
+  sum = wave_sum(sum);
+  if (lane == 0) s_part[w] = sum;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float t = 0.0f;
+    for (int i = 0; i < kWaves; ++i) t += s_part[i];
+    partial[blockIdx.x] = t;
+  }
+}
+
+// Final reduction of the per-workgroup partials in FP64.
+__global__ __launch_bounds__(1024) void reduce_partials_f64(const float* __restrict__ partial,
+                                                          int count, double* __restrict__ out) {
+  __shared__ double s[1024 / kWave];
+  double t = 0.0;
+  for (int i = threadIdx.x; i < count; i += blockDim.x) t += static_cast<double>(partial[i]);
+  for (int d = 32; d >= 1; d >>= 1) t += __shfl_xor(t, d);
+  if ((threadIdx.x & 63) == 0) s[threadIdx.x / kWave] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double u = 0.0;
+    for (int i = 0; i < static_cast<int>(blockDim.x) / kWave; ++i) u += s[i];
+    out[0] = u;
+  }
+}
+
+__global__ void fill_f32_kernel(float* __restrict__ p, int64_t n) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t k = i; k < n; k += stride) p[k] = 0.0f;
+}
+
+template <typename XT, bool kSym>
+int launch_csr_typed(int n, int nnz, const int32_t* rowptr, const int32_t* col,
+                     const float* val, const XT* x, float* y, hipStream_t s) {
+  const int64_t tiles = (static_cast<int64_t>(n) + nnz + kTile - 1) / kTile;
+  const int64_t blocks = (tiles + kWaves - 1) / kWaves;
+  if (blocks == 0) return SYSTEC_OK;
+  LaunchTimer timer(s);
+  csr_tiles_kernel<XT, kSym><<<dim3(blocks), dim3(kBlock), 0, s>>>(n, nnz, rowptr, col, val, x, y);
+  return check_launch(kSym ? "ssymv kernel" : "spmv kernel");
+}
+
+}  // namespace
+
+int launch_fill_f32(float* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return SYSTEC_OK;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 8192);
+  fill_f32_kernel<<<dim3(blocks), dim3(256), 0, s>>>(p, n);
+  return check_launch("fill kernel");
+}
+
+int launch_ssymv(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col,
+                 const float* val, const void* x, systec_dtype xdt, float* y, bool symmetric,
+                 hipStream_t s) {
+  int rc = launch_fill_f32(y, n, s);
+  if (rc != SYSTEC_OK || nnz == 0) return rc;
+  const int ni = static_cast<int>(n), nz = static_cast<int>(nnz);
+  if (xdt == SYSTEC_F32) {
+    const float* xf = static_cast<const float*>(x);
+    return symmetric ? launch_csr_typed<float, true>(ni, nz, rowptr, col, val, xf, y, s)
+                     : launch_csr_typed<float, false>(ni, nz, rowptr, col, val, xf, y, s);
+  }
+  const uint16_t* xb = static_cast<const uint16_t*>(x);
+  return symmetric ? launch_csr_typed<uint16_t, true>(ni, nz, rowptr, col, val, xb, y, s)
+                   : launch_csr_typed<uint16_t, false>(ni, nz, rowptr, col, val, xb, y, s);
+}
+
+int launch_syprd(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col,
+                 const float* val, const void* x, systec_dtype xdt, double* out,
+                 hipStream_t s) {
+  const int64_t tiles = (n + nnz + kTile - 1) / kTile;
+  const int64_t blocks = std::max<int64_t>(1, (tiles + kWaves - 1) / kWaves);
+  float* partial = nullptr;
+  int rc = check_hip(hipMallocAsync(reinterpret_cast<void**>(&partial), blocks * sizeof(float), s),
+                     "hipMallocAsync(syprd partials)");
+  if (rc != SYSTEC_OK) return rc;
+  const int ni = static_cast<int>(n), nz = static_cast<int>(nnz);
+  {
+    LaunchTimer timer(s);
+    if (xdt == SYSTEC_F32)
+      syprd_tiles_kernel<float><<<dim3(blocks), dim3(kBlock), 0, s>>>(
+          ni, nz, rowptr, col, val, static_cast<const float*>(x), partial);
+    else
+      syprd_tiles_kernel<uint16_t><<<dim3(blocks), dim3(kBlock), 0, s>>>(
+          ni, nz, rowptr, col, val, static_cast<const uint16_t*>(x), partial);
+    rc = check_launch("syprd kernel");
+  }
+  if (rc == SYSTEC_OK) {
+    reduce_partials_f64<<<dim3(1), dim3(1024), 0, s>>>(partial, static_cast<int>(blocks), out);
+    rc = check_launch("syprd final reduction");
+  }
+  const int rc2 = check_hip(hipFreeAsync(partial, s), "hipFreeAsync(syprd partials)");
+  return rc != SYSTEC_OK ? rc : rc2;
+}
+
+}  // namespace systec
