@@ -213,6 +213,45 @@ SYSTEC_API int systec_canonicalize_coo(int order, int64_t nnz, int32_t* const* i
 SYSTEC_API int systec_quantize_bf16(const float* in, uint16_t* out, int64_t n, systec_stream stream);
 
 /* ------------------------------------------------------------------------
+ * Prepared operands. A symmetric operand can be rearranged once on the
+ * device into a layout that turns the scattered output updates into
+ * segmented reductions (the data rearrangement the paper keeps outside its
+ * timings, Sec. 5.2, and the symmetry-aware storage it names as future work,
+ * Sec. 7). The canonical entries are kept, only reordered:
+ *  - matrix: rows cut into panels of 16384 rows; inside a panel the stored
+ *    entries are sorted by (column, row). systec_ssymv_t keeps the panel's
+ *    row sums in LDS and reduces the column side by segments.
+ *  - tensor of order 3..5: one slot view per index slot t, holding the
+ *    entries whose slot t starts a run of equal indices, sorted by their
+ *    slot-t index. systec_mttkrp_t reduces every view by segments.
+ * The handle owns a device copy (systec_tensor_info reports its bytes); the
+ * caller's buffers may be freed after create returns. Create validates the
+ * canonical form on the device (SYSTEC_ENONCANON if it does not hold),
+ * synchronizes `stream`, and returns SYSTEC_ENOMEM if the copy does not fit.
+ * The handle may be used from any stream of the device it was created on;
+ * calls that share a handle only read it.
+ * ---------------------------------------------------------------------- */
+typedef struct systec_tensor systec_tensor;
+
+SYSTEC_API int systec_tensor_create_csr(int64_t n, int64_t nnz, const int32_t* rowptr,
+                                        const int32_t* col, const float* val,
+                                        systec_stream stream, systec_tensor** out);
+SYSTEC_API int systec_tensor_create_coo(int order, int64_t I, int64_t nnz,
+                                        const int32_t* const* idx, const float* val,
+                                        systec_stream stream, systec_tensor** out);
+/* order (2 for a matrix), dim (n or I), stored nnz, effective nnz (entries of
+ * the expanded tensor), device bytes held. Any output pointer may be NULL. */
+SYSTEC_API int systec_tensor_info(const systec_tensor* t, int* order, int64_t* dim,
+                                  int64_t* nnz, int64_t* effective_nnz, uint64_t* bytes);
+SYSTEC_API int systec_tensor_destroy(systec_tensor* t);
+/* y = A x for a prepared matrix; x, y as for systec_ssymv. */
+SYSTEC_API int systec_ssymv_t(const systec_tensor* t, const void* x, systec_dtype xdt, float* y,
+                              systec_stream stream);
+/* C = MTTKRP for a prepared tensor; B, C as for systec_mttkrp. */
+SYSTEC_API int systec_mttkrp_t(const systec_tensor* t, const void* B, systec_dtype bdt,
+                               int64_t R, float* C, systec_stream stream);
+
+/* ------------------------------------------------------------------------
  * Kernel timing. When enabled, the library records a pair of HIP events
  * around every launch of a hot kernel (SSYMV, SYPRD, MTTKRP and the
  * comparison kernels) on the stream it is launched on.

@@ -23,7 +23,7 @@ from ._lib import SYSTEC_BF16, SYSTEC_F32, SystecError, call, ptr_array
 __all__ = [
     "SystecError", "ssymv", "syprd", "mttkrp", "spmv_csr", "mttkrp_full", "expand_csr",
     "expand_coo", "expansion_stats", "validate_csr_upper", "validate_coo",
-    "canonicalize_coo", "quantize_bf16", "KernelTimer", "version",
+    "canonicalize_coo", "quantize_bf16", "KernelTimer", "version", "Tensor",
 ]
 
 
@@ -231,6 +231,75 @@ def quantize_bf16(x, out=None, stream=None):
     y = out if out is not None else torch.empty(x.shape, dtype=torch.bfloat16, device=x.device)
     call("systec_quantize_bf16", _p(x), _p(y), x.numel(), _stream(stream))
     return y
+
+
+class Tensor:
+    """A prepared symmetric operand (library-owned device copy, rearranged
+    once so that every output update is a segmented reduction).
+
+        A = Tensor.from_csr(rowptr, col, val)     # upper-triangle CSR
+        y = A.ssymv(x)
+        T = Tensor.from_coo([i1, i2, i3], val, I)  # canonical COO, order 3..5
+        C = T.mttkrp(B)
+    """
+
+    def __init__(self, handle):
+        self._h = handle
+        order, dim, nnz, eff, nbytes = (ctypes.c_int(), ctypes.c_int64(), ctypes.c_int64(),
+                                        ctypes.c_int64(), ctypes.c_uint64())
+        call("systec_tensor_info", self._h, ctypes.byref(order), ctypes.byref(dim),
+             ctypes.byref(nnz), ctypes.byref(eff), ctypes.byref(nbytes))
+        self.order, self.dim, self.nnz = order.value, dim.value, nnz.value
+        self.effective_nnz, self.bytes = eff.value, nbytes.value
+
+    @classmethod
+    def from_csr(cls, rowptr, col, val, stream=None):
+        torch = _torch()
+        _dev(rowptr, torch.int32, "rowptr"), _dev(col, torch.int32, "col")
+        _dev(val, torch.float32, "val")
+        h = ctypes.c_void_p()
+        call("systec_tensor_create_csr", rowptr.numel() - 1, col.numel(), _p(rowptr), _p(col),
+             _p(val), _stream(stream), ctypes.byref(h))
+        return cls(h)
+
+    @classmethod
+    def from_coo(cls, idx, val, I, stream=None):
+        torch = _torch()
+        _dev(val, torch.float32, "val")
+        pp, keep = _idx_ptrs(idx)
+        h = ctypes.c_void_p()
+        call("systec_tensor_create_coo", len(idx), I, val.numel(), pp, _p(val), _stream(stream),
+             ctypes.byref(h))
+        del keep
+        return cls(h)
+
+    def ssymv(self, x, out=None, stream=None):
+        torch = _torch()
+        _dev(x, None, "x")
+        y = out if out is not None else torch.empty(self.dim, dtype=torch.float32, device=x.device)
+        call("systec_ssymv_t", self._h, _p(x), _dtype_code(x), _p(y), _stream(stream))
+        return y
+
+    def mttkrp(self, B, out=None, stream=None):
+        torch = _torch()
+        _dev(B, None, "B")
+        I, R = B.shape
+        if I != self.dim:
+            raise ValueError("B must have one row per tensor index")
+        C = out if out is not None else torch.empty((I, R), dtype=torch.float32, device=B.device)
+        call("systec_mttkrp_t", self._h, _p(B), _dtype_code(B), R, _p(C), _stream(stream))
+        return C
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            _lib.lib().systec_tensor_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class KernelTimer:

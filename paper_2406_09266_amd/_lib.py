@@ -43,6 +43,13 @@ SIGNATURES = {
     "systec_validate_coo": [I32, I64, I64, PP, P],
     "systec_canonicalize_coo": [I32, I64, PP, P, PI64],
     "systec_quantize_bf16": [P, P, I64, P],
+    "systec_tensor_create_csr": [I64, I64, P, P, P, P, PP],
+    "systec_tensor_create_coo": [I32, I64, I64, PP, P, P, PP],
+    "systec_tensor_info": [P, ctypes.POINTER(ctypes.c_int), PI64, PI64, PI64,
+                           ctypes.POINTER(ctypes.c_uint64)],
+    "systec_tensor_destroy": [P],
+    "systec_ssymv_t": [P, P, I32, P, P],
+    "systec_mttkrp_t": [P, P, I32, I64, P, P],
     "systec_kernel_timing": [I32],
     "systec_kernel_timing_read": [PD, PI64],
 }

@@ -113,6 +113,10 @@ LaunchTimer::~LaunchTimer() {
 
 using namespace systec;
 
+struct systec_tensor {
+  systec::Tensor* impl;
+};
+
 extern "C" {
 
 const char* systec_last_error(void) { return g_last_error.c_str(); }
@@ -330,6 +334,74 @@ int systec_quantize_bf16(const float* in, uint16_t* out, int64_t n, systec_strea
   if (n < 0) return fail(SYSTEC_EINVAL, "systec_quantize_bf16: n < 0");
   if (n > 0 && (!in || !out)) return fail(SYSTEC_EINVAL, "systec_quantize_bf16: NULL pointer");
   return launch_quantize_bf16(in, out, n, static_cast<hipStream_t>(stream));
+}
+
+int systec_tensor_create_csr(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col,
+                             const float* val, systec_stream stream, systec_tensor** out) {
+  int rc = check_csr_args("systec_tensor_create_csr", n, nnz, rowptr, col, val, rowptr,
+                          SYSTEC_F32, out);
+  if (rc) return rc;
+  if ((rc = systec_validate_csr_upper(n, nnz, rowptr, col, stream))) return rc;
+  auto s = static_cast<hipStream_t>(stream);
+  int64_t full = 0;
+  if (nnz > 0 && (rc = expand_csr_size(n, nnz, rowptr, col, &full, s))) return rc;
+  Tensor* t = nullptr;
+  if ((rc = tensor_create_csr(n, nnz, rowptr, col, val, 16384, s, &t))) return rc;
+  t->effective_nnz = full;
+  *out = new systec_tensor{t};
+  return SYSTEC_OK;
+}
+
+int systec_tensor_create_coo(int order, int64_t I, int64_t nnz, const int32_t* const* idx,
+                             const float* val, systec_stream stream, systec_tensor** out) {
+  int rc = check_coo_args("systec_tensor_create_coo", order, 3, I, nnz, idx, val);
+  if (rc) return rc;
+  if (!out) return fail(SYSTEC_EINVAL, "systec_tensor_create_coo: NULL output");
+  if ((rc = systec_validate_coo(order, I, nnz, idx, stream))) return rc;
+  auto s = static_cast<hipStream_t>(stream);
+  int64_t hist[16], eff = 0;
+  if (nnz > 0 && (rc = systec_expansion_stats(order, I, nnz, idx, hist, &eff, stream))) return rc;
+  Tensor* t = nullptr;
+  if ((rc = tensor_create_coo(order, I, nnz, idx, val, s, &t))) return rc;
+  t->effective_nnz = eff;
+  *out = new systec_tensor{t};
+  return SYSTEC_OK;
+}
+
+int systec_tensor_info(const systec_tensor* t, int* order, int64_t* dim, int64_t* nnz,
+                       int64_t* effective_nnz, uint64_t* bytes) {
+  if (!t || !t->impl) return fail(SYSTEC_EINVAL, "systec_tensor_info: NULL handle");
+  if (order) *order = t->impl->order;
+  if (dim) *dim = t->impl->dim;
+  if (nnz) *nnz = t->impl->nnz;
+  if (effective_nnz) *effective_nnz = t->impl->effective_nnz;
+  if (bytes) *bytes = t->impl->bytes;
+  return SYSTEC_OK;
+}
+
+int systec_tensor_destroy(systec_tensor* t) {
+  if (!t) return SYSTEC_OK;
+  tensor_free(t->impl);
+  delete t;
+  return SYSTEC_OK;
+}
+
+int systec_ssymv_t(const systec_tensor* t, const void* x, systec_dtype xdt, float* y,
+                   systec_stream stream) {
+  if (!t || !t->impl) return fail(SYSTEC_EINVAL, "systec_ssymv_t: NULL handle");
+  if (t->impl->kind != 0) return fail(SYSTEC_EINVAL, "systec_ssymv_t: not a matrix");
+  if (!valid_dtype(xdt)) return fail(SYSTEC_EINVAL, "systec_ssymv_t: unsupported dtype");
+  if (!x || !y) return fail(SYSTEC_EINVAL, "systec_ssymv_t: NULL pointer");
+  return launch_ssymv_panel(t->impl, x, xdt, y, static_cast<hipStream_t>(stream));
+}
+
+int systec_mttkrp_t(const systec_tensor* t, const void* B, systec_dtype bdt, int64_t R,
+                    float* C, systec_stream stream) {
+  if (!t || !t->impl) return fail(SYSTEC_EINVAL, "systec_mttkrp_t: NULL handle");
+  if (t->impl->kind != 1) return fail(SYSTEC_EINVAL, "systec_mttkrp_t: not an order-3..5 tensor");
+  int rc = check_factor_args("systec_mttkrp_t", t->impl->dim, B, bdt, R, C);
+  if (rc) return rc;
+  return launch_mttkrp_views(t->impl, B, bdt, R, C, static_cast<hipStream_t>(stream));
 }
 
 int systec_kernel_timing(int enable) {

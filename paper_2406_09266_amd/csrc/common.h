@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "systec.h"
 
@@ -76,6 +77,50 @@ int expand_coo_size(int order, int64_t I, int64_t nnz, const int32_t* const* idx
                     int64_t* full_nnz, hipStream_t s);
 int expand_coo(int order, int64_t I, int64_t nnz, const int32_t* const* idx, const float* val,
                int32_t* const* out_idx, float* out_val, hipStream_t s);
+
+// ---- prepared operands (plan.hip) -------------------------------------------
+// A matrix in the symmetric panel format: the stored upper triangle cut into
+// panels of H consecutive rows; inside a panel the entries are sorted by
+// (column, row) and padded to a multiple of kPanelTile entries (padding:
+// value 0 on the panel's first diagonal position). The kernel keeps the
+// panel's row sums in LDS and reduces the column side by segments.
+// A tensor as slot views: for each slot t, the canonical entries whose slot t
+// starts a run of equal indices, sorted by their slot-t index (stable), so
+// that every output update of view t is a segmented reduction.
+constexpr int kPanelTile = 512;
+struct Tensor {
+  int kind = 0;  // 0: matrix (panel format), 1: tensor (slot views)
+  int order = 0;
+  int64_t dim = 0;
+  int64_t nnz = 0;
+  int64_t effective_nnz = 0;
+  uint64_t bytes = 0;
+  // matrix
+  int panel_rows = 0;
+  int npanels = 0;
+  int64_t padded = 0;
+  int32_t* pcol = nullptr;
+  uint16_t* prow = nullptr;
+  float* pval = nullptr;
+  int nchunks = 0;
+  int32_t* chunk_panel = nullptr;
+  int32_t* chunk_tile_begin = nullptr;
+  int32_t* chunk_tile_end = nullptr;
+  // tensor
+  int64_t vnnz[5] = {0, 0, 0, 0, 0};
+  int32_t* vidx[5][5] = {};
+  float* vval[5] = {};
+  std::vector<void*> allocations;
+};
+int tensor_create_csr(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col,
+                      const float* val, int panel_rows, hipStream_t s, Tensor** out);
+int tensor_create_coo(int order, int64_t I, int64_t nnz, const int32_t* const* idx,
+                      const float* val, hipStream_t s, Tensor** out);
+void tensor_free(Tensor* t);
+int launch_ssymv_panel(const Tensor* t, const void* x, systec_dtype xdt, float* y,
+                       hipStream_t s);
+int launch_mttkrp_views(const Tensor* t, const void* B, systec_dtype bdt, int64_t R, float* C,
+                        hipStream_t s);
 
 // ---- multiplicity rule (host and device) ----------------------------------
 // For a sorted tuple of `order` indices whose equality pattern is `mask`

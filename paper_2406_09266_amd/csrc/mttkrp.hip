@@ -119,6 +119,56 @@ __global__ __launch_bounds__(kBlock) void mttkrp_tiles_kernel(int nnz, IdxPtrs i
   if (cur >= 0 && col_ok) atomic_add_noret(C + static_cast<int64_t>(cur) * ldc + col, acc);
 }
 
+// MTTKRP over one slot view of a prepared tensor (see plan.hip): every entry
+// of view t updates C[c_t] with its slot-t coefficient, and the view is sorted
+// by c_t, so all updates are register accumulations written once per run.
+template <int N, typename BT, int L>
+__global__ __launch_bounds__(kBlock) void mttkrp_view_kernel(int t, int nnz, IdxPtrs idx,
+                                                           const float* __restrict__ val,
+                                                           const BT* __restrict__ B, int ldb,
+                                                           float* __restrict__ C, int ldc,
+                                                           int col0, int ncols) {
+  constexpr int G = kWave / L;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int g = lane / L;
+  const int cl = lane - g * L;
+  const bool col_ok = cl < ncols;
+  const int col = col0 + (col_ok ? cl : 0);
+  const int64_t wave = static_cast<int64_t>(blockIdx.x) * kWaves + threadIdx.x / kWave;
+  const int64_t e_begin = wave * kTileE;
+  if (e_begin >= nnz) return;
+  const int e_end = static_cast<int>(min<int64_t>(nnz, e_begin + kTileE));
+
+  int cur = -1;
+  float acc = 0.0f;
+  for (int e = static_cast<int>(e_begin) + g; e < e_end; e += G) {
+    int c[N];
+#pragma unroll
+    for (int s = 0; s < N; ++s) c[s] = idx.p[s][e];
+    const float v = val[e];
+    int mask = 0;
+#pragma unroll
+    for (int s = 0; s + 1 < N; ++s) mask |= (c[s] == c[s + 1]) ? (1 << s) : 0;
+    float prod = coef_table<N>().coef[mask][t] * v;
+    int out = c[0];
+#pragma unroll
+    for (int s = 0; s < N; ++s) {
+      if (s == t) {
+        out = c[s];
+      } else {
+        prod *= load_f32(B, static_cast<int64_t>(c[s]) * ldb + col);
+      }
+    }
+    if (out != cur) {
+      if (cur >= 0 && col_ok) atomic_add_noret(C + static_cast<int64_t>(cur) * ldc + col, acc);
+      cur = out;
+      acc = 0.0f;
+    }
+    acc += prod;
+  }
+  if (cur >= 0 && col_ok) atomic_add_noret(C + static_cast<int64_t>(cur) * ldc + col, acc);
+}
+
 template <int N, typename BT, int L, bool kSym>
 void launch_one(int nnz, const IdxPtrs& ip, const float* val, const BT* B, int ldb, float* C,
                 int ldc, int col0, int ncols, hipStream_t s) {
@@ -181,6 +231,60 @@ int launch_mttkrp(int order, int64_t I, int64_t nnz, const int32_t* const* idx,
       break;
   }
   return check_launch(symmetric ? "mttkrp kernel" : "mttkrp (full) kernel");
+}
+
+namespace {
+
+template <int N, typename BT, int L>
+void launch_view_one(int t, int nnz, const IdxPtrs& ip, const float* val, const BT* B, int ldb,
+                     float* C, int ldc, int col0, int ncols, hipStream_t s) {
+  const int64_t tiles = (static_cast<int64_t>(nnz) + kTileE - 1) / kTileE;
+  const int64_t blocks = (tiles + kWaves - 1) / kWaves;
+  if (blocks == 0) return;
+  mttkrp_view_kernel<N, BT, L>
+      <<<dim3(blocks), dim3(kBlock), 0, s>>>(t, nnz, ip, val, B, ldb, C, ldc, col0, ncols);
+}
+
+template <int N, typename BT>
+void launch_views_typed(const Tensor* tn, const BT* B, int R, float* C, hipStream_t s) {
+  for (int t = 0; t < N; ++t) {
+    const int m = static_cast<int>(tn->vnnz[t]);
+    if (m == 0) continue;
+    IdxPtrs ip{};
+    for (int q = 0; q < N; ++q) ip.p[q] = tn->vidx[t][q];
+    const float* val = tn->vval[t];
+    if (R <= 8) launch_view_one<N, BT, 8>(t, m, ip, val, B, R, C, R, 0, R, s);
+    else if (R <= 16) launch_view_one<N, BT, 16>(t, m, ip, val, B, R, C, R, 0, R, s);
+    else if (R <= 32) launch_view_one<N, BT, 32>(t, m, ip, val, B, R, C, R, 0, R, s);
+    else
+      for (int c0 = 0; c0 < R; c0 += 64)
+        launch_view_one<N, BT, 64>(t, m, ip, val, B, R, C, R, c0, std::min(64, R - c0), s);
+  }
+}
+
+template <int N>
+void launch_views_order(const Tensor* tn, const void* B, systec_dtype bdt, int R, float* C,
+                        hipStream_t s) {
+  if (bdt == SYSTEC_F32)
+    launch_views_typed<N, float>(tn, static_cast<const float*>(B), R, C, s);
+  else
+    launch_views_typed<N, uint16_t>(tn, static_cast<const uint16_t*>(B), R, C, s);
+}
+
+}  // namespace
+
+int launch_mttkrp_views(const Tensor* t, const void* B, systec_dtype bdt, int64_t R, float* C,
+                        hipStream_t s) {
+  int rc = launch_fill_f32(C, t->dim * R, s);
+  if (rc != SYSTEC_OK || t->nnz == 0) return rc;
+  const int r = static_cast<int>(R);
+  LaunchTimer timer(s);
+  switch (t->order) {
+    case 3: launch_views_order<3>(t, B, bdt, r, C, s); break;
+    case 4: launch_views_order<4>(t, B, bdt, r, C, s); break;
+    default: launch_views_order<5>(t, B, bdt, r, C, s); break;
+  }
+  return check_launch("mttkrp view kernels");
 }
 
 }  // namespace systec

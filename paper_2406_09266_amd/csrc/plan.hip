@@ -1,0 +1,372 @@
+// Prepared operands: the canonical entries rearranged once into a layout
+// that lets every output update become a register or LDS reduction.
+//
+// This is the data rearrangement the paper keeps outside its timings
+// (Sec. 5.2: rearranging data before or after a kernel is not timed) and the
+// symmetry-aware format it names as future work (Sec. 7). Both layouts keep
+// only canonical entries; they change their order, not their meaning.
+//
+// Matrix panel format. Rows are cut into panels of H rows. Inside a panel the
+// stored entries (i <= j) are sorted by (j, i). The SSYMV kernel then keeps
+// the panel's row sums y[i] in LDS, and the column-side updates y[j] += a x[i]
+// arrive sorted by j, so they reduce by segments and leave the workgroup as
+// one atomic per (panel, column) instead of one per entry.
+//
+// Tensor slot views. For MTTKRP, view t holds the canonical entries whose
+// slot t starts a run of equal indices (the slots that receive an update,
+// Sec. 4.3), stably sorted by their slot-t index. Every update of view t goes
+// to C[c_t], so a view is reduced by segments like a CSR row, without
+// scattered atomics.
+#include "common.h"
+
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <vector>
+
+namespace systec {
+namespace {
+
+constexpr int kChunkTiles = 64;  // panel tiles per workgroup work item
+
+int grid_for(int64_t n, int block) {
+  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>((n + block - 1) / block, 8192)));
+}
+
+// entry -> row by binary search over rowptr
+__global__ void entry_rows_kernel(int n, int nnz, const int32_t* __restrict__ rowptr,
+                                  int32_t* __restrict__ rows) {
+  const int stride = gridDim.x * blockDim.x;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += stride) {
+    int lo = 0, hi = n;  // rowptr[lo] <= e < rowptr[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (rowptr[mid] <= e) lo = mid;
+      else hi = mid;
+    }
+    rows[e] = lo;
+  }
+}
+
+// sort key of a stored entry: (panel, column, row within panel)
+__global__ void panel_keys_kernel(int nnz, int hbits, const int32_t* __restrict__ rows,
+                                  const int32_t* __restrict__ col,
+                                  unsigned long long* __restrict__ keys,
+                                  uint32_t* __restrict__ ids) {
+  const int stride = gridDim.x * blockDim.x;
+  const unsigned long long hmask = (1ull << hbits) - 1;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += stride) {
+    const unsigned long long r = static_cast<uint32_t>(rows[e]);
+    const unsigned long long c = static_cast<uint32_t>(col[e]);
+    keys[e] = ((r >> hbits) << (31 + hbits)) | (c << hbits) | (r & hmask);
+    ids[e] = static_cast<uint32_t>(e);
+  }
+}
+
+__global__ void panel_count_kernel(int nnz, int hbits, const unsigned long long* __restrict__ keys,
+                                   int32_t* __restrict__ counts) {
+  const int stride = gridDim.x * blockDim.x;
+  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < nnz; s += stride) {
+    const int p = static_cast<int>(keys[s] >> (31 + hbits));
+    atomicAdd(&counts[p], 1);
+  }
+}
+
+__global__ void panel_scatter_kernel(int nnz, int hbits, const unsigned long long* __restrict__ keys,
+                                     const uint32_t* __restrict__ ids,
+                                     const float* __restrict__ val,
+                                     const int32_t* __restrict__ start,
+                                     const int32_t* __restrict__ pstart,
+                                     int32_t* __restrict__ pcol, uint16_t* __restrict__ prow,
+                                     float* __restrict__ pval) {
+  const int stride = gridDim.x * blockDim.x;
+  const unsigned long long hmask = (1ull << hbits) - 1;
+  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < nnz; s += stride) {
+    const unsigned long long k = keys[s];
+    const int p = static_cast<int>(k >> (31 + hbits));
+    const int64_t dst = static_cast<int64_t>(pstart[p]) + (s - start[p]);
+    pcol[dst] = static_cast<int32_t>((k >> hbits) & 0x7fffffffull);
+    prow[dst] = static_cast<uint16_t>(k & hmask);
+    pval[dst] = val[ids[s]];
+  }
+}
+
+// padding of panel p: positions [pstart[p] + count[p], pstart[p+1])
+__global__ void panel_pad_kernel(int npanels, int H, const int32_t* __restrict__ counts,
+                                 const int32_t* __restrict__ pstart, int32_t* __restrict__ pcol,
+                                 uint16_t* __restrict__ prow, float* __restrict__ pval) {
+  for (int p = blockIdx.x; p < npanels; p += gridDim.x) {
+    const int64_t b = static_cast<int64_t>(pstart[p]) + counts[p];
+    const int64_t e = pstart[p + 1];
+    for (int64_t q = b + threadIdx.x; q < e; q += blockDim.x) {
+      pcol[q] = p * H;  // the panel's first row: a diagonal position, value 0
+      prow[q] = 0;
+      pval[q] = 0.0f;
+    }
+  }
+}
+
+// ---- slot views ----
+__global__ void view_keys_kernel(int order, int t, int nnz, const int32_t* i0, const int32_t* i1,
+                                 const int32_t* i2, const int32_t* i3, const int32_t* i4,
+                                 uint32_t* __restrict__ keys, uint32_t* __restrict__ ids,
+                                 int* __restrict__ count) {
+  const int32_t* ip[5] = {i0, i1, i2, i3, i4};
+  const int stride = gridDim.x * blockDim.x;
+  int c = 0;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += stride) {
+    const int v = ip[t][e];
+    const bool starts = (t == 0) || (ip[t - 1][e] != v);
+    keys[e] = starts ? static_cast<uint32_t>(v) : 0xffffffffu;  // non-starts sort last
+    ids[e] = static_cast<uint32_t>(e);
+    c += starts;
+  }
+  for (int d = 32; d >= 1; d >>= 1) c += __shfl_xor(c, d);
+  if ((threadIdx.x & 63) == 0 && c) atomicAdd(count, c);
+}
+
+__global__ void view_gather_kernel(int order, int m, const uint32_t* __restrict__ ids,
+                                   const int32_t* i0, const int32_t* i1, const int32_t* i2,
+                                   const int32_t* i3, const int32_t* i4,
+                                   const float* __restrict__ val, int32_t* o0, int32_t* o1,
+                                   int32_t* o2, int32_t* o3, int32_t* o4,
+                                   float* __restrict__ oval) {
+  const int32_t* ip[5] = {i0, i1, i2, i3, i4};
+  int32_t* op[5] = {o0, o1, o2, o3, o4};
+  const int stride = gridDim.x * blockDim.x;
+  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < m; s += stride) {
+    const uint32_t e = ids[s];
+    for (int t = 0; t < order; ++t) op[t][s] = ip[t][e];
+    oval[s] = val[e];
+  }
+}
+
+struct Scratch {
+  std::vector<void*> ptrs;
+  ~Scratch() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+  template <typename T>
+  int alloc(T** p, size_t count) {
+    void* q = nullptr;
+    int rc = check_hip(hipMalloc(&q, std::max<size_t>(1, count) * sizeof(T)), "hipMalloc");
+    if (rc) return rc;
+    ptrs.push_back(q);
+    *p = static_cast<T*>(q);
+    return SYSTEC_OK;
+  }
+};
+
+template <typename T>
+int tensor_alloc(Tensor* t, T** p, size_t count) {
+  void* q = nullptr;
+  const size_t bytes = std::max<size_t>(1, count) * sizeof(T);
+  hipError_t e = hipMalloc(&q, bytes);
+  if (e != hipSuccess) return fail(SYSTEC_ENOMEM, std::string("hipMalloc (prepared operand): ") + hipGetErrorString(e));
+  t->allocations.push_back(q);
+  t->bytes += bytes;
+  *p = static_cast<T*>(q);
+  return SYSTEC_OK;
+}
+
+template <typename K>
+int radix_sort_pairs(const K* kin, K* kout, const uint32_t* vin, uint32_t* vout, int n,
+                     int end_bit, hipStream_t s) {
+  size_t tmp_bytes = 0;
+  int rc = check_hip(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, kin, kout, vin, vout,
+                                                        n, 0, end_bit, s),
+                     "radix sort (size)");
+  if (rc) return rc;
+  Scratch sc;
+  unsigned char* tmp = nullptr;
+  if ((rc = sc.alloc(&tmp, tmp_bytes))) return rc;
+  rc = check_hip(hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, kin, kout, vin, vout, n, 0,
+                                                    end_bit, s),
+                 "radix sort");
+  if (!rc) rc = check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+  return rc;
+}
+
+int bits_for(int64_t v) {
+  int b = 0;
+  while ((int64_t(1) << b) < v) ++b;
+  return std::max(b, 1);
+}
+
+}  // namespace
+
+void tensor_free(Tensor* t) {
+  if (!t) return;
+  for (void* p : t->allocations) (void)hipFree(p);
+  delete t;
+}
+
+int tensor_create_csr(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col,
+                      const float* val, int panel_rows, hipStream_t s, Tensor** out) {
+  const int hbits = bits_for(panel_rows);
+  const int H = 1 << hbits;
+  auto* t = new Tensor();
+  t->kind = 0;
+  t->order = 2;
+  t->dim = n;
+  t->nnz = nnz;
+  t->panel_rows = H;
+  t->npanels = static_cast<int>((n + H - 1) / H);
+  const int P = t->npanels;
+  const int nz = static_cast<int>(nnz), ni = static_cast<int>(n);
+  Scratch sc;
+  int32_t* rows = nullptr;
+  unsigned long long *kin = nullptr, *kout = nullptr;
+  uint32_t *vin = nullptr, *vout = nullptr;
+  int32_t *counts = nullptr, *d_start = nullptr, *d_pstart = nullptr;
+  int rc = sc.alloc(&rows, nnz);
+  if (!rc) rc = sc.alloc(&kin, nnz);
+  if (!rc) rc = sc.alloc(&kout, nnz);
+  if (!rc) rc = sc.alloc(&vin, nnz);
+  if (!rc) rc = sc.alloc(&vout, nnz);
+  if (!rc) rc = sc.alloc(&counts, P);
+  if (!rc) rc = sc.alloc(&d_start, P + 1);
+  if (!rc) rc = sc.alloc(&d_pstart, P + 1);
+  if (rc) {
+    tensor_free(t);
+    return rc;
+  }
+  std::vector<int32_t> h_counts(P, 0);
+  // counts must be zero even without entries: the padding kernel reads them
+  rc = check_hip(hipMemsetAsync(counts, 0, P * sizeof(int32_t), s), "hipMemsetAsync");
+  if (rc) {
+    tensor_free(t);
+    return rc;
+  }
+  if (nnz > 0) {
+    entry_rows_kernel<<<grid_for(nnz, 256), 256, 0, s>>>(ni, nz, rowptr, rows);
+    panel_keys_kernel<<<grid_for(nnz, 256), 256, 0, s>>>(nz, hbits, rows, col, kin, vin);
+    rc = check_launch("panel key kernels");
+    if (!rc) rc = radix_sort_pairs(kin, kout, vin, vout, nz, 31 + hbits + bits_for(P + 1), s);
+    if (!rc) {
+      panel_count_kernel<<<grid_for(nnz, 256), 256, 0, s>>>(nz, hbits, kout, counts);
+      rc = check_launch("panel count kernel");
+    }
+    if (!rc)
+      rc = check_hip(hipMemcpyAsync(h_counts.data(), counts, P * sizeof(int32_t),
+                                    hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+    if (!rc) rc = check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+    if (rc) {
+      tensor_free(t);
+      return rc;
+    }
+  }
+  // padded panel offsets and the chunk table (host, P is small)
+  std::vector<int32_t> h_start(P + 1, 0), h_pstart(P + 1, 0);
+  std::vector<int32_t> ch_panel, ch_begin, ch_end;
+  int64_t pos = 0, ppos = 0;
+  for (int p = 0; p < P; ++p) {
+    h_start[p] = static_cast<int32_t>(pos);
+    h_pstart[p] = static_cast<int32_t>(ppos);
+    const int64_t tiles = (h_counts[p] + kPanelTile - 1) / kPanelTile;
+    const int64_t tile0 = ppos / kPanelTile;
+    for (int64_t c = 0; c < tiles; c += kChunkTiles) {
+      ch_panel.push_back(p);
+      ch_begin.push_back(static_cast<int32_t>(tile0 + c));
+      ch_end.push_back(static_cast<int32_t>(tile0 + std::min<int64_t>(tiles, c + kChunkTiles)));
+    }
+    pos += h_counts[p];
+    ppos += tiles * kPanelTile;
+  }
+  h_start[P] = static_cast<int32_t>(pos);
+  h_pstart[P] = static_cast<int32_t>(ppos);
+  if (ppos > (int64_t(1) << 31) - 1) {
+    tensor_free(t);
+    return fail(SYSTEC_EINVAL, "prepared matrix too large for int32 offsets");
+  }
+  t->padded = ppos;
+  t->nchunks = static_cast<int>(ch_panel.size());
+  rc = tensor_alloc(t, &t->pcol, ppos);
+  if (!rc) rc = tensor_alloc(t, &t->prow, ppos);
+  if (!rc) rc = tensor_alloc(t, &t->pval, ppos);
+  if (!rc) rc = tensor_alloc(t, &t->chunk_panel, t->nchunks);
+  if (!rc) rc = tensor_alloc(t, &t->chunk_tile_begin, t->nchunks);
+  if (!rc) rc = tensor_alloc(t, &t->chunk_tile_end, t->nchunks);
+  const size_t pb = (P + 1) * sizeof(int32_t);
+  if (!rc) rc = check_hip(hipMemcpyAsync(d_start, h_start.data(), pb, hipMemcpyHostToDevice, s), "memcpy");
+  if (!rc) rc = check_hip(hipMemcpyAsync(d_pstart, h_pstart.data(), pb, hipMemcpyHostToDevice, s), "memcpy");
+  const size_t cb = t->nchunks * sizeof(int32_t);
+  if (!rc && t->nchunks) {
+    rc = check_hip(hipMemcpyAsync(t->chunk_panel, ch_panel.data(), cb, hipMemcpyHostToDevice, s), "memcpy");
+    if (!rc) rc = check_hip(hipMemcpyAsync(t->chunk_tile_begin, ch_begin.data(), cb, hipMemcpyHostToDevice, s), "memcpy");
+    if (!rc) rc = check_hip(hipMemcpyAsync(t->chunk_tile_end, ch_end.data(), cb, hipMemcpyHostToDevice, s), "memcpy");
+  }
+  if (!rc && nnz > 0) {
+    panel_scatter_kernel<<<grid_for(nnz, 256), 256, 0, s>>>(nz, hbits, kout, vout, val, d_start,
+                                                            d_pstart, t->pcol, t->prow, t->pval);
+    rc = check_launch("panel scatter kernel");
+  }
+  if (!rc && P > 0) {
+    panel_pad_kernel<<<std::min(P, 4096), 256, 0, s>>>(P, H, counts, d_pstart, t->pcol, t->prow,
+                                                      t->pval);
+    rc = check_launch("panel pad kernel");
+  }
+  if (!rc) rc = check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+  if (rc) {
+    tensor_free(t);
+    return rc;
+  }
+  *out = t;
+  return SYSTEC_OK;
+}
+
+int tensor_create_coo(int order, int64_t I, int64_t nnz, const int32_t* const* idx,
+                      const float* val, hipStream_t s, Tensor** out) {
+  auto* t = new Tensor();
+  t->kind = 1;
+  t->order = order;
+  t->dim = I;
+  t->nnz = nnz;
+  const int nz = static_cast<int>(nnz);
+  const int32_t* ip[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  for (int q = 0; q < order; ++q) ip[q] = idx[q];
+  Scratch sc;
+  uint32_t *kin = nullptr, *kout = nullptr, *vin = nullptr, *vout = nullptr;
+  int* d_count = nullptr;
+  int rc = sc.alloc(&kin, nnz);
+  if (!rc) rc = sc.alloc(&kout, nnz);
+  if (!rc) rc = sc.alloc(&vin, nnz);
+  if (!rc) rc = sc.alloc(&vout, nnz);
+  if (!rc) rc = sc.alloc(&d_count, 1);
+  for (int v = 0; v < order && !rc; ++v) {
+    int m = 0;
+    if (nnz > 0) {
+      rc = check_hip(hipMemsetAsync(d_count, 0, sizeof(int), s), "hipMemsetAsync");
+      if (rc) break;
+      view_keys_kernel<<<grid_for(nnz, 256), 256, 0, s>>>(order, v, nz, ip[0], ip[1], ip[2],
+                                                          ip[3], ip[4], kin, vin, d_count);
+      if ((rc = check_launch("view key kernel"))) break;
+      if ((rc = radix_sort_pairs(kin, kout, vin, vout, nz, 32, s))) break;
+      if ((rc = check_hip(hipMemcpyAsync(&m, d_count, sizeof(int), hipMemcpyDeviceToHost, s),
+                          "hipMemcpyAsync")))
+        break;
+      if ((rc = check_hip(hipStreamSynchronize(s), "hipStreamSynchronize"))) break;
+    }
+    t->vnnz[v] = m;
+    for (int q = 0; q < order && !rc; ++q) rc = tensor_alloc(t, &t->vidx[v][q], m);
+    if (!rc) rc = tensor_alloc(t, &t->vval[v], m);
+    if (rc) break;
+    if (m > 0) {
+      int32_t* op[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+      for (int q = 0; q < order; ++q) op[q] = t->vidx[v][q];
+      view_gather_kernel<<<grid_for(m, 256), 256, 0, s>>>(order, m, vout, ip[0], ip[1], ip[2],
+                                                          ip[3], ip[4], val, op[0], op[1], op[2],
+                                                          op[3], op[4], t->vval[v]);
+      if ((rc = check_launch("view gather kernel"))) break;
+      if ((rc = check_hip(hipStreamSynchronize(s), "hipStreamSynchronize"))) break;
+    }
+  }
+  if (rc) {
+    tensor_free(t);
+    return rc;
+  }
+  *out = t;
+  return SYSTEC_OK;
+}
+
+}  // namespace systec

@@ -78,6 +78,26 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
+// Finishes a wave's segmented sums. Each lane has summed its own entries by
+// key (keys nondecreasing across lanes): segments strictly inside the lane are
+// already written; `first_key`/`head_val` is its first segment when the lane
+// holds more than one (nseg >= 2) and `tail_key`/`tail` its last one. The
+// last segments are combined across lanes with a segmented scan; a segment
+// that continues into the next lane is written by the lane where it ends.
+__device__ __forceinline__ void flush_lane_segments(int lane, int first_key, int tail_key,
+                                                    float tail_part, float head_val, int nseg,
+                                                    float* __restrict__ y) {
+  const float tail = wave_seg_sum(tail_key, tail_part);
+  const int prev_key = __shfl_up(tail_key, 1);
+  const float prev_tail = __shfl_up(tail, 1);
+  const int next_first = __shfl_down(first_key, 1);
+  if (nseg >= 2) {
+    const float c = (lane > 0 && prev_key == first_key) ? prev_tail : 0.0f;
+    atomic_add_noret(y + first_key, head_val + c);
+  }
+  if (lane == kWave - 1 || next_first != tail_key) atomic_add_noret(y + tail_key, tail);
+}
+
 // Merge-path split (Merrill & Garland's merge-based CSR decomposition): the
 // rows' end offsets and the entry indices form one sorted sequence of n + nnz
 // items; diagonal d of it splits at the largest row i in [0, n] with
@@ -237,17 +257,7 @@ __global__ __launch_bounds__(kBlock) void csr_tiles_kernel(int n, int nnz,
       if (kSym && c != r) atomic_add_noret(y + c, a * xr);
     }
   }
-  // segments that cross lanes
-  const int tail_key = cur;
-  const float tail = wave_seg_sum(tail_key, acc);
-  const int prev_key = __shfl_up(tail_key, 1);
-  const float prev_tail = __shfl_up(tail, 1);
-  const int next_first = __shfl_down(first_key, 1);
-  if (nseg >= 2) {
-    const float c = (lane > 0 && prev_key == first_key) ? prev_tail : 0.0f;
-    atomic_add_noret(y + first_key, head_val + c);
-  }
-  if (lane == kWave - 1 || next_first != tail_key) atomic_add_noret(y + tail_key, tail);
+  flush_lane_segments(lane, first_key, cur, acc, head_val, nseg, y);
 }
 
 // SYPRD partial sums: one FP32 partial per workgroup.
@@ -299,6 +309,66 @@ __global__ __launch_bounds__(1024) void reduce_partials_f64(const float* __restr
     double u = 0.0;
     for (int i = 0; i < static_cast<int>(blockDim.x) / kWave; ++i) u += s[i];
     out[0] = u;
+  }
+}
+
+// SSYMV over a matrix in the panel format (see plan.hip). One workgroup per
+// chunk of one panel: the panel's row sums live in LDS (H floats); the
+// entries arrive sorted by column, so the column-side updates reduce by
+// segments across each lane and wave before their atomic.
+template <typename XT>
+__global__ __launch_bounds__(512) void ssymv_panel_kernel(
+    int n, int H, const int32_t* __restrict__ chunk_panel,
+    const int32_t* __restrict__ chunk_tile_begin, const int32_t* __restrict__ chunk_tile_end,
+    const int32_t* __restrict__ pcol, const uint16_t* __restrict__ prow,
+    const float* __restrict__ pval, const XT* __restrict__ x, float* __restrict__ y) {
+  extern __shared__ float s_rows[];  // the panel's row sums
+  const int chunk = blockIdx.x;
+  const int p = chunk_panel[chunk];
+  const int tb = chunk_tile_begin[chunk], te = chunk_tile_end[chunk];
+  const int r0 = p * H;
+  for (int i = threadIdx.x; i < H; i += blockDim.x) s_rows[i] = 0.0f;
+  __syncthreads();
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
+  const int nw = blockDim.x / kWave;
+  for (int tile = tb + w; tile < te; tile += nw) {
+    const int64_t base = static_cast<int64_t>(tile) * kTile + lane * kV;
+    int c[kV];
+    read8(pcol + base, c);
+    const int4 rr = *reinterpret_cast<const int4*>(prow + base);
+    const uint16_t ro[kV] = {
+        static_cast<uint16_t>(rr.x & 0xffff), static_cast<uint16_t>(static_cast<uint32_t>(rr.x) >> 16),
+        static_cast<uint16_t>(rr.y & 0xffff), static_cast<uint16_t>(static_cast<uint32_t>(rr.y) >> 16),
+        static_cast<uint16_t>(rr.z & 0xffff), static_cast<uint16_t>(static_cast<uint32_t>(rr.z) >> 16),
+        static_cast<uint16_t>(rr.w & 0xffff), static_cast<uint16_t>(static_cast<uint32_t>(rr.w) >> 16)};
+    const float4 va = reinterpret_cast<const float4*>(pval + base)[0];
+    const float4 vb = reinterpret_cast<const float4*>(pval + base)[1];
+    const float a[kV] = {va.x, va.y, va.z, va.w, vb.x, vb.y, vb.z, vb.w};
+
+    const int first_key = c[0];
+    int cur = c[0];
+    float acc = 0.0f, head_val = 0.0f;
+    int nseg = 1;
+#pragma unroll
+    for (int k = 0; k < kV; ++k) {
+      const int r = r0 + ro[k];
+      if (a[k] != 0.0f) atomicAdd(s_rows + ro[k], a[k] * load_f32(x, c[k]));  // y[i] += a x[j]
+      if (c[k] != cur) {
+        if (nseg == 1) head_val = acc;
+        else atomic_add_noret(y + cur, acc);
+        ++nseg;
+        cur = c[k];
+        acc = 0.0f;
+      }
+      if (c[k] != r) acc += a[k] * load_f32(x, r);  // y[j] += a x[i], j > i
+    }
+    flush_lane_segments(lane, first_key, cur, acc, head_val, nseg, y);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < H; i += blockDim.x) {
+    const float v = s_rows[i];
+    if (v != 0.0f && r0 + i < n) atomic_add_noret(y + r0 + i, v);
   }
 }
 
@@ -370,6 +440,24 @@ int launch_syprd(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* c
   }
   const int rc2 = check_hip(hipFreeAsync(partial, s), "hipFreeAsync(syprd partials)");
   return rc != SYSTEC_OK ? rc : rc2;
+}
+
+int launch_ssymv_panel(const Tensor* t, const void* x, systec_dtype xdt, float* y,
+                       hipStream_t s) {
+  int rc = launch_fill_f32(y, t->dim, s);
+  if (rc != SYSTEC_OK || t->nchunks == 0) return rc;
+  const size_t lds = static_cast<size_t>(t->panel_rows) * sizeof(float);
+  const int n = static_cast<int>(t->dim);
+  LaunchTimer timer(s);
+  if (xdt == SYSTEC_F32)
+    ssymv_panel_kernel<float><<<dim3(t->nchunks), dim3(512), lds, s>>>(
+        n, t->panel_rows, t->chunk_panel, t->chunk_tile_begin, t->chunk_tile_end, t->pcol,
+        t->prow, t->pval, static_cast<const float*>(x), y);
+  else
+    ssymv_panel_kernel<uint16_t><<<dim3(t->nchunks), dim3(512), lds, s>>>(
+        n, t->panel_rows, t->chunk_panel, t->chunk_tile_begin, t->chunk_tile_end, t->pcol,
+        t->prow, t->pval, static_cast<const uint16_t*>(x), y);
+  return check_launch("ssymv panel kernel");
 }
 
 }  // namespace systec

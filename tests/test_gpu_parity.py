@@ -232,8 +232,9 @@ def test_full_coo_comparison_kernel(order):
 
 @pytest.mark.parametrize("order", [2, 3, 4, 5])
 def test_expansion_stats_bit_exact(order):
-    t = synth.sym_coo(order, 4000 if order == 2 else 60, 20000 if order > 2 else 30000,
-                      0.02 if order == 2 else 0.3, seed=300 + order)
+    dim = {2: 4000, 3: 300, 4: 80, 5: 40}[order]
+    t = synth.sym_coo(order, dim, 20000 if order > 2 else 30000, 0.02 if order == 2 else 0.3,
+                      seed=300 + order)
     hist, eff = systec.expansion_stats([dev(a) for a in t["idx"]], t["dim"])
     r = oracle.expand(order, t["dim"], t["idx"].T)
     assert eff == r["effective_nnz"]

@@ -1,0 +1,151 @@
+"""GPU parity of the prepared operands (panel format for matrices, slot views
+for tensors) against the FP64 oracle; same tolerances as test_gpu_parity."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2406_09266_amd as systec
+from paper_2406_09266_amd import synth
+
+from gpu_util import dev, f32, rel_err
+
+pytestmark = pytest.mark.gpu
+TOL32 = 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    yield
+    torch.cuda.synchronize()
+
+
+def _x(m, xdtype):
+    x = dev(m["x"].astype(np.float32))
+    if xdtype == "bf16":
+        return systec.quantize_bf16(x), oracle.round_bf16(m["x"].astype(np.float32))
+    return x, f32(m["x"])
+
+
+MATRICES = {
+    "small_n2000": lambda: synth.workload("ssymv_small"),
+    "uniform_n40000_ragged_panels": lambda: synth.ssymv_uniform(40001, 9, seed=51),
+    "rmat_scale16": lambda: synth.ssymv_rmat(scale=16, batch=1 << 18, seed=52),
+    "rmat_scale15_relabel": lambda: synth.ssymv_rmat(scale=15, batch=1 << 17, seed=53,
+                                                     relabel=True),
+    "diagonal_only": lambda: synth.ssymv_uniform(20000, 0, seed=54),
+}
+
+
+@pytest.mark.parametrize("case", sorted(MATRICES))
+@pytest.mark.parametrize("xdtype", ["f32", "bf16"])
+def test_prepared_ssymv(case, xdtype):
+    m = MATRICES[case]()
+    print(f"prepared ssymv case={case} x={xdtype} n={m['n']} nnz={m['col'].size}", flush=True)
+    A = systec.Tensor.from_csr(dev(m["rowptr"]), dev(m["col"]), dev(m["val"].astype(np.float32)))
+    x, xref = _x(m, xdtype)
+    y = A.ssymv(x).cpu().numpy()
+    want, counts = oracle.ssymv(m["n"], m["rowptr"], m["col"], f32(m["val"]), xref)
+    assert rel_err(y, want) <= TOL32
+    assert A.effective_nnz == counts["effective_nnz"] and A.nnz == m["col"].size
+    assert A.order == 2 and A.bytes > 0
+    # a second call on the same handle gives the same result within tolerance
+    y2 = A.ssymv(x).cpu().numpy()
+    assert rel_err(y2, y) <= TOL32
+    A.close()
+
+
+def test_prepared_ssymv_empty_rows_and_panels():
+    import torch
+    # rows only in the last panel; earlier panels empty
+    n = 50000
+    rowptr = np.zeros(n + 1, dtype=np.int32)
+    rowptr[n - 100:] = np.arange(0, 101, dtype=np.int32)  # rows n-100.. hold one entry each
+    cols = np.arange(n - 100, n, dtype=np.int32)           # on the diagonal
+    m = {"n": n, "rowptr": rowptr, "col": cols, "val": synth.dense_uniform(100, seed=1),
+         "x": synth.dense_uniform(n, seed=2)}
+    A = systec.Tensor.from_csr(dev(m["rowptr"]), dev(m["col"]), dev(m["val"].astype(np.float32)))
+    x, xref = _x(m, "f32")
+    y = A.ssymv(x).cpu().numpy()
+    want, _ = oracle.ssymv(n, m["rowptr"], m["col"], f32(m["val"]), xref)
+    assert rel_err(y, want) <= TOL32
+    # nnz = 0
+    E = systec.Tensor.from_csr(dev(np.zeros(11, np.int32)), torch.empty(0, dtype=torch.int32,
+                               device="cuda"), torch.empty(0, device="cuda"))
+    ye = E.ssymv(dev(np.ones(10, np.float32)), out=torch.full((10,), 5.0, device="cuda"))
+    assert torch.count_nonzero(ye).item() == 0
+
+
+def test_prepared_rejects_noncanonical():
+    m = synth.ssymv_uniform(300, 5, seed=3)
+    col = m["col"].copy()
+    col[m["rowptr"][7]] = 2
+    with pytest.raises(systec.SystecError) as e:
+        systec.Tensor.from_csr(dev(m["rowptr"]), dev(col), dev(m["val"].astype(np.float32)))
+    assert e.value.status_name == "SYSTEC_ENONCANON"
+    t = synth.sym_coo(3, 50, 500, 0.1, seed=4)
+    bad = t["idx"].copy()
+    bad[:, [3, 4]] = bad[:, [4, 3]]
+    with pytest.raises(systec.SystecError):
+        systec.Tensor.from_coo([dev(a) for a in bad], dev(t["val"].astype(np.float32)), 50)
+
+
+@pytest.mark.parametrize("order,dim,nnz", [(3, 400, 30011), (4, 150, 20021), (5, 70, 12007)])
+@pytest.mark.parametrize("R", [1, 16, 32, 70])
+@pytest.mark.parametrize("bdtype", ["f32", "bf16"])
+def test_prepared_mttkrp(order, dim, nnz, R, bdtype):
+    t = synth.sym_coo(order, dim, nnz, repeat_frac=0.2, seed=2000 + order * 11 + R)
+    B = synth.dense_uniform((dim, R), seed=R + 1)
+    T = systec.Tensor.from_coo([dev(a) for a in t["idx"]], dev(t["val"].astype(np.float32)), dim)
+    Bd = dev(B.astype(np.float32))
+    Bref = f32(B)
+    if bdtype == "bf16":
+        Bd = systec.quantize_bf16(Bd)
+        Bref = oracle.round_bf16(B.astype(np.float32))
+    C = T.mttkrp(Bd).cpu().numpy()
+    want, counts = oracle.mttkrp(order, dim, t["idx"].T, f32(t["val"]), Bref)
+    assert rel_err(C, want) <= TOL32
+    assert T.effective_nnz == counts["effective_nnz"]
+    T.close()
+
+
+@pytest.mark.parametrize("order", [3, 5])
+def test_prepared_mttkrp_all_diagonal(order):
+    dim = 900
+    idx = np.stack([np.arange(dim, dtype=np.int32)] * order)
+    val = synth.dense_uniform(dim, seed=9)
+    B = synth.dense_uniform((dim, 16), seed=10)
+    T = systec.Tensor.from_coo([dev(a) for a in idx], dev(val.astype(np.float32)), dim)
+    C = T.mttkrp(dev(B.astype(np.float32))).cpu().numpy()
+    want, _ = oracle.mttkrp(order, dim, idx.T, f32(val), f32(B))
+    assert rel_err(C, want) <= TOL32
+
+
+def test_prepared_full_size_ssymv_rmat():
+    m = synth.workload("ssymv_rmat")
+    A = systec.Tensor.from_csr(dev(m["rowptr"]), dev(m["col"]), dev(m["val"].astype(np.float32)))
+    for xdtype in ("bf16", "f32"):
+        x, xref = _x(m, xdtype)
+        y = A.ssymv(x).cpu().numpy()
+        want, counts = oracle.ssymv(m["n"], m["rowptr"], m["col"], f32(m["val"]), xref)
+        assert rel_err(y, want) <= TOL32, xdtype
+    assert A.effective_nnz == counts["effective_nnz"]
+
+
+@pytest.mark.parametrize("name", ["mttkrp3", "mttkrp5"])
+def test_prepared_full_size_mttkrp_sampled(name):
+    t = synth.workload(name)
+    I = t["dim"]
+    T = systec.Tensor.from_coo([dev(a) for a in t["idx"]], dev(t["val"].astype(np.float32)), I)
+    rng = np.random.Generator(np.random.PCG64(6))
+    rows = np.unique(np.concatenate([[0, I - 1], rng.integers(0, I, 200)]))
+    mask = np.zeros(I, np.uint8)
+    mask[rows] = 1
+    Bd = systec.quantize_bf16(dev(t["B"].astype(np.float32)))
+    C = T.mttkrp(Bd).cpu().numpy()
+    want, counts = oracle.mttkrp(t["order"], I, t["idx"].T, f32(t["val"]),
+                                 oracle.round_bf16(t["B"].astype(np.float32)), row_mask=mask)
+    assert rel_err(C[rows], want[rows]) <= TOL32
+    assert T.effective_nnz == counts["effective_nnz"]
