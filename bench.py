@@ -41,7 +41,13 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="ssymv_rmat",
-                    choices=["ssymv_rmat", "ssymv_small", "mttkrp3", "mttkrp5"])
+                    choices=["ssymv_rmat", "ssymv_small", "mttkrp3", "mttkrp5", "served_mix"])
+    ap.add_argument("--pool-per-kind", type=int, default=8,
+                    help="served_mix: resident tensors per kind (SSYMV, 3-D, 4-D)")
+    ap.add_argument("--requests", type=int, default=1000,
+                    help="served_mix: requests per Poisson run")
+    ap.add_argument("--loads", default="0.5,0.8,0.95",
+                    help="served_mix: offered loads as fractions of saturation")
     ap.add_argument("--form", default="bf16", choices=["f32", "bf16"],
                     help="storage of x / B (arithmetic is FP32 either way)")
     ap.add_argument("--path", default="prepared", choices=["prepared", "oneshot"],
@@ -119,6 +125,9 @@ def main():
     from paper_2406_09266_amd import synth
 
     dev = torch.device("cuda:0")
+    if a.workload == "served_mix":
+        served_mix(a, torch, systec, synth, dev)
+        return
     t_gen = time.perf_counter()
     w = synth.workload(a.workload)
     t_gen = time.perf_counter() - t_gen
@@ -276,6 +285,155 @@ def main():
         out["oracle_rel_err"] = err
     out["setup_s"] = {"generate": round(t_gen, 2), "prepare_operand": round(t_prep, 3)}
     print(json.dumps(out), flush=True)
+
+
+def served_mix(a, torch, systec, synth, dev):
+    """Poisson arrivals of mixed SSYMV / 3-D / 4-D MTTKRP requests against
+    resident prepared tensors: the BF16 continuous-batching server versus the
+    plain FP32 form (one request at a time, synchronous, FIFO) on the same
+    arrival trace. Reports saturation throughput and p50/p99 latency
+    (arrival to completion, queueing included) at each offered load."""
+    import math
+    rng = np.random.Generator(np.random.PCG64(5))
+    K = a.pool_per_kind
+    t0 = time.perf_counter()
+    pool = []  # (kind, operand on device, effective nnz)
+    for k in range(K):
+        n = int(math.exp(rng.uniform(math.log(1e4), math.log(2e6))))
+        deg = rng.uniform(8, 32)
+        pool.append(("ssymv", synth.gpu_ssymv_random(n, deg, seed=100 + k, device=dev)))
+    for order in (3, 4):
+        for k in range(K):
+            I = int(math.exp(rng.uniform(math.log(1e3), math.log(2e5))))
+            nnz = int(math.exp(rng.uniform(math.log(1e4), math.log(5e7))))
+            nnz = min(nnz, int(0.3 * math.comb(I + order - 1, order)))
+            pool.append((f"mttkrp{order}",
+                         synth.gpu_sym_coo(order, I, nnz, 0.01, seed=200 + 10 * order + k,
+                                           device=dev)))
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+
+    def prepare(item):
+        kind, op = item
+        if kind == "ssymv":
+            return systec.Tensor.from_csr(op["rowptr"], op["col"], op["val"])
+        return systec.Tensor.from_coo(op["idx"], op["val"], op["dim"])
+
+    t0 = time.perf_counter()
+    served_t = [prepare(it) for it in pool]
+    plain_t = [prepare(it) for it in pool]
+    t_prep = time.perf_counter() - t0
+    eff = [t.effective_nnz for t in served_t]
+    dims = [t.dim for t in served_t]
+    kinds = [it[0] for it in pool]
+    resident = sum(t.bytes for t in served_t)
+    # inputs: one per (tensor, R), FP32 and BF16
+    Rs = (8, 16, 32)
+    inputs = {}
+    for p, (kind, op) in enumerate(pool):
+        g = torch.Generator(device=dev)
+        g.manual_seed(300 + p)
+        shapes = [(dims[p],)] if kind == "ssymv" else [(dims[p], R) for R in Rs]
+        for shp in shapes:
+            x = torch.rand(shp, generator=g, device=dev) * 2 - 1
+            inputs[(p, shp[-1] if len(shp) == 2 else 1)] = (x, systec.quantize_bf16(x))
+    torch.cuda.synchronize()
+
+    by_kind = {}
+    for p, k in enumerate(kinds):
+        by_kind.setdefault(k, []).append(p)
+    kind_names = sorted(by_kind)
+
+    def draw(count, seed):
+        r = np.random.Generator(np.random.PCG64(seed))
+        reqs = []
+        for _ in range(count):
+            k = kind_names[int(r.integers(0, len(kind_names)))]
+            p = by_kind[k][int(r.integers(0, len(by_kind[k])))]
+            R = 1 if k == "ssymv" else int(r.choice(Rs))
+            reqs.append((p, R))
+        return reqs
+
+    budget = 200 << 30
+    srv = systec.Server(budget_bytes=budget, max_slots=32, step_work_nnz=1 << 24)
+    ids = [srv.register(t) for t in served_t]
+
+    def out_for(p, R):
+        return torch.empty((dims[p],) if R == 1 else (dims[p], R), device=dev)
+
+    def run_served(reqs, arrivals_s):
+        """Submits at the scheduled times; returns the server stats."""
+        srv.reset_stats()
+        outs = []
+        base = systec.Server.now_ns()
+        for (p, R), t_arr in zip(reqs, arrivals_s):
+            due = base + int(t_arr * 1e9)
+            while systec.Server.now_ns() < due:
+                pass
+            x = inputs[(p, R)][1]
+            outs.append(srv.submit(ids[p], x, out_for(p, R), arrival_ns=due))
+        for rid in outs:
+            srv.wait(rid, 600_000_000)
+        return srv.stats()
+
+    def run_plain(reqs, arrivals_s):
+        lat = []
+        base = systec.Server.now_ns()
+        last = base
+        for (p, R), t_arr in zip(reqs, arrivals_s):
+            due = base + int(t_arr * 1e9)
+            while systec.Server.now_ns() < due:
+                pass
+            x = inputs[(p, R)][0]
+            t = plain_t[p]
+            if kinds[p] == "ssymv":
+                t.ssymv(x, out=out_for(p, 1))
+            else:
+                t.mttkrp(x, out=out_for(p, R))
+            torch.cuda.synchronize()
+            last = systec.Server.now_ns()
+            lat.append((last - due) * 1e-3)
+        lat.sort()
+        pct = lambda q: lat[max(0, min(len(lat) - 1, math.ceil(q / 100 * len(lat)) - 1))]  # noqa
+        span = (last - base) * 1e-9
+        eff_done = sum(eff[p] for p, _ in reqs)
+        return {"p50_us": pct(50), "p99_us": pct(99), "req_per_s": len(lat) / span,
+                "eff_nnz_per_s": eff_done / span}
+
+    # warm-up, then saturation (everything arrives at once)
+    run_served(draw(64, 1), [0.0] * 64)
+    n_sat = max(200, a.requests // 3)
+    sat_reqs = draw(n_sat, 2)
+    st = run_served(sat_reqs, [0.0] * n_sat)
+    sat = st["req_per_s"]
+    plain_sat = run_plain(sat_reqs, [0.0] * n_sat)
+    result = {"metric": "served p50/p99 latency (us) and throughput, BF16 continuous batching "
+                        "vs plain FP32 one request at a time",
+              "workload": "served_mix", "n_gpus": 1, "data": "synthetic (device generators)",
+              "pool": {"tensors": len(pool), "per_kind": K, "resident_bytes": resident,
+                       "budget_bytes": budget, "effective_nnz_total": int(sum(eff)),
+                       "generate_s": round(t_gen, 2), "prepare_s": round(t_prep, 2)},
+              "saturation": {"served_req_per_s": sat, "served_eff_nnz_per_s": st["eff_nnz_per_s"],
+                             "plain_req_per_s": plain_sat["req_per_s"],
+                             "plain_eff_nnz_per_s": plain_sat["eff_nnz_per_s"],
+                             "requests": n_sat},
+              "loads": []}
+    for frac in [float(v) for v in a.loads.split(",") if v]:
+        lam = frac * sat
+        r = np.random.Generator(np.random.PCG64(int(frac * 1000)))
+        arr = np.cumsum(r.exponential(1.0 / lam, a.requests))
+        reqs = draw(a.requests, int(frac * 1000) + 7)
+        s1 = run_served(reqs, arr)
+        p1 = run_plain(reqs, arr)
+        result["loads"].append({
+            "load": frac, "lambda_req_per_s": lam,
+            "served": {"p50_us": s1["p50_us"], "p99_us": s1["p99_us"],
+                       "req_per_s": s1["req_per_s"], "eff_nnz_per_s": s1["eff_nnz_per_s"],
+                       "steps": s1["steps"], "failed": s1["failed"]},
+            "plain": p1})
+        print(json.dumps({"progress": f"load {frac} done"}), flush=True)
+    srv.close()
+    print(json.dumps(result), flush=True)
 
 
 def _cpu_model():

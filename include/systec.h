@@ -252,6 +252,61 @@ SYSTEC_API int systec_mttkrp_t(const systec_tensor* t, const void* B, systec_dty
                                int64_t R, float* C, systec_stream stream);
 
 /* ------------------------------------------------------------------------
+ * Serving: many prepared operands resident in HBM, requests of mixed kind
+ * and size batched continuously into persistent launches.
+ *
+ * A server owns a stream on `device` and a scheduler thread. Registered
+ * tensors (systec_serve_register takes ownership of a systec_tensor; it is
+ * freed by the server) count against budget_bytes while registered. A
+ * request names a registered tensor, an input (x for a matrix, B with R
+ * columns for a tensor; dtype F32 or BF16) and an output (y or C, FP32) in
+ * device memory; their bytes are charged from admission to completion.
+ * Requests are admitted in arrival order while fewer than max_slots are
+ * running and the bytes fit; a request that could never fit returns
+ * SYSTEC_EBUDGET from submit, and more than max_queue waiting requests
+ * return SYSTEC_EBUSY. Each step takes work (chunks of the prepared
+ * operands, at most step_work_nnz entries in total) from every running
+ * request round-robin and runs it as one persistent kernel launch; a
+ * request submitted while a step runs joins the next step. The output is
+ * zeroed by the server; it is complete when wait returns SYSTEC_OK or poll
+ * reports state 2. Latency is measured from arrival_ns (a time from
+ * systec_serve_now_ns; 0 means "now") to completion, so it includes
+ * queueing. In and out buffers must stay valid until the request completes
+ * or fails. R is limited to 1..64. A failed step marks every request in it
+ * failed (state 3; wait returns SYSTEC_EDEVICE with the message).
+ * destroy fails queued requests, drains running ones and frees the tensors.
+ * ---------------------------------------------------------------------- */
+typedef struct systec_server systec_server;
+typedef struct {
+  uint64_t budget_bytes;  /* resident tensors + in-flight request buffers */
+  int32_t max_slots;      /* requests running at once */
+  int64_t step_work_nnz;  /* work per step, in stored entries */
+  int32_t device;         /* HIP device ordinal */
+  int32_t max_queue;      /* waiting requests before SYSTEC_EBUSY (<= 0: 2^20) */
+} systec_serve_config;
+typedef struct {
+  int64_t submitted, completed, failed, rejected, steps, queued, running;
+  double p50_us, p99_us, mean_us, max_us; /* latency of completed requests */
+  double req_per_s, eff_nnz_per_s;        /* from first arrival to last completion */
+  uint64_t bytes_in_use;
+} systec_serve_stats;
+
+SYSTEC_API int systec_serve_create(const systec_serve_config* cfg, systec_server** out);
+SYSTEC_API int systec_serve_register(systec_server* s, systec_tensor* t, int64_t* tensor_id);
+SYSTEC_API int systec_serve_unregister(systec_server* s, int64_t tensor_id);
+SYSTEC_API int systec_serve_submit(systec_server* s, int64_t tensor_id, const void* in,
+                                   systec_dtype dt, int64_t R, float* out, int64_t arrival_ns,
+                                   int64_t* req_id);
+/* state: 0 queued, 1 running, 2 done, 3 failed */
+SYSTEC_API int systec_serve_poll(systec_server* s, int64_t req_id, int* state);
+/* timeout_us < 0 waits without limit; SYSTEC_ETIMEOUT when it expires */
+SYSTEC_API int systec_serve_wait(systec_server* s, int64_t req_id, int64_t timeout_us);
+SYSTEC_API int systec_serve_get_stats(systec_server* s, systec_serve_stats* out);
+SYSTEC_API int systec_serve_reset_stats(systec_server* s);
+SYSTEC_API int64_t systec_serve_now_ns(void);
+SYSTEC_API int systec_serve_destroy(systec_server* s);
+
+/* ------------------------------------------------------------------------
  * Kernel timing. When enabled, the library records a pair of HIP events
  * around every launch of a hot kernel (SSYMV, SYPRD, MTTKRP and the
  * comparison kernels) on the stream it is launched on.

@@ -23,7 +23,7 @@ from ._lib import SYSTEC_BF16, SYSTEC_F32, SystecError, call, ptr_array
 __all__ = [
     "SystecError", "ssymv", "syprd", "mttkrp", "spmv_csr", "mttkrp_full", "expand_csr",
     "expand_coo", "expansion_stats", "validate_csr_upper", "validate_coo",
-    "canonicalize_coo", "quantize_bf16", "KernelTimer", "version", "Tensor",
+    "canonicalize_coo", "quantize_bf16", "KernelTimer", "version", "Tensor", "Server",
 ]
 
 
@@ -121,7 +121,12 @@ def mttkrp(idx, val, B, out=None, stream=None):
     order = len(idx)
     I, R = B.shape
     _dev(B, None, "B"), _dev(val, torch.float32, "val")
+    if any(t.numel() != val.numel() for t in idx):
+        raise ValueError("index arrays and values must have the same length")
     C = out if out is not None else torch.empty((I, R), dtype=torch.float32, device=B.device)
+    _dev(C, torch.float32, "out")
+    if tuple(C.shape) != (I, R):
+        raise ValueError("out must be I x R")
     pp, keep = _idx_ptrs(idx)
     call("systec_mttkrp", order, I, val.numel(), pp, _p(val), _p(B), _dtype_code(B), R, _p(C),
          _stream(stream))
@@ -276,6 +281,8 @@ class Tensor:
     def ssymv(self, x, out=None, stream=None):
         torch = _torch()
         _dev(x, None, "x")
+        if self.order != 2 or x.numel() != self.dim or (out is not None and out.numel() != self.dim):
+            raise ValueError("ssymv needs a prepared matrix and x, y of n elements")
         y = out if out is not None else torch.empty(self.dim, dtype=torch.float32, device=x.device)
         call("systec_ssymv_t", self._h, _p(x), _dtype_code(x), _p(y), _stream(stream))
         return y
@@ -284,9 +291,12 @@ class Tensor:
         torch = _torch()
         _dev(B, None, "B")
         I, R = B.shape
-        if I != self.dim:
+        if I != self.dim or self.order < 3:
             raise ValueError("B must have one row per tensor index")
         C = out if out is not None else torch.empty((I, R), dtype=torch.float32, device=B.device)
+        _dev(C, torch.float32, "out")
+        if tuple(C.shape) != (I, R):
+            raise ValueError("out must be I x R")
         call("systec_mttkrp_t", self._h, _p(B), _dtype_code(B), R, _p(C), _stream(stream))
         return C
 
@@ -294,6 +304,103 @@ class Tensor:
         if self._h is not None and self._h.value:
             _lib.lib().systec_tensor_destroy(self._h)
         self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching server over prepared operands resident in HBM.
+
+        srv = Server(budget_bytes=200 << 30, max_slots=16)
+        tid = srv.register(Tensor.from_csr(rowptr, col, val))   # ownership moves
+        req = srv.submit(tid, x, y)        # y = A x, asynchronous
+        srv.wait(req)
+        srv.stats()                        # p50/p99 latency, throughput
+
+    Input and output buffers are kept alive by the server object until the
+    request has completed (wait() or poll() saw it finish)."""
+
+    QUEUED, RUNNING, DONE, FAILED = 0, 1, 2, 3
+
+    def __init__(self, budget_bytes=200 << 30, max_slots=16, step_work_nnz=1 << 24, device=None,
+                 max_queue=0):
+        torch = _torch()
+        cfg = _lib.ServeConfig(budget_bytes, max_slots, step_work_nnz,
+                               torch.cuda.current_device() if device is None else device,
+                               max_queue)
+        self._h = ctypes.c_void_p()
+        call("systec_serve_create", ctypes.byref(cfg), ctypes.byref(self._h))
+        self._live = {}
+        self._kind = {}
+
+    @staticmethod
+    def now_ns():
+        return int(_lib.lib().systec_serve_now_ns())
+
+    def register(self, tensor):
+        tid = ctypes.c_int64()
+        call("systec_serve_register", self._h, tensor._h, ctypes.byref(tid))
+        tensor._h = None  # owned by the server now
+        self._kind[tid.value] = (tensor.order, tensor.dim, tensor.effective_nnz)
+        return tid.value
+
+    def submit(self, tensor_id, inp, out, arrival_ns=0):
+        torch = _torch()
+        _dev(inp, None, "input"), _dev(out, torch.float32, "output")
+        R = 1 if inp.dim() == 1 else inp.shape[1]
+        order, dim, _ = self._kind.get(tensor_id, (None, None, None))
+        if order == 2:
+            if inp.numel() != dim or out.numel() != dim:
+                raise ValueError("x and y must have n elements")
+        elif order is not None:
+            if inp.dim() != 2 or inp.shape[0] != dim or tuple(out.shape) != (dim, R):
+                raise ValueError("B must be I x R and C I x R")
+        rid = ctypes.c_int64()
+        call("systec_serve_submit", self._h, tensor_id, _p(inp), _dtype_code(inp), R, _p(out),
+             int(arrival_ns), ctypes.byref(rid))
+        self._live[rid.value] = (inp, out)
+        return rid.value
+
+    def poll(self, req):
+        st = ctypes.c_int()
+        call("systec_serve_poll", self._h, req, ctypes.byref(st))
+        if st.value in (self.DONE, self.FAILED):
+            self._live.pop(req, None)
+        return st.value
+
+    def wait(self, req, timeout_us=-1):
+        try:
+            call("systec_serve_wait", self._h, req, int(timeout_us))
+        except SystecError as e:
+            if e.status_name != "SYSTEC_ETIMEOUT":
+                self._live.pop(req, None)
+            raise
+        self._live.pop(req, None)
+
+    def stats(self):
+        st = _lib.ServeStats()
+        call("systec_serve_get_stats", self._h, ctypes.byref(st))
+        return {name: getattr(st, name) for name, _ in st._fields_}
+
+    def reset_stats(self):
+        call("systec_serve_reset_stats", self._h)
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            _lib.lib().systec_serve_destroy(self._h)
+        self._h = None
+        self._live.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
 
     def __del__(self):
         try:

@@ -53,7 +53,36 @@ SIGNATURES = {
     "systec_kernel_timing": [I32],
     "systec_kernel_timing_read": [PD, PI64],
 }
-_RESTYPE = {"systec_last_error": ctypes.c_char_p, "systec_version": ctypes.c_char_p}
+
+
+class ServeConfig(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_uint64), ("max_slots", ctypes.c_int32),
+                ("step_work_nnz", ctypes.c_int64), ("device", ctypes.c_int32),
+                ("max_queue", ctypes.c_int32)]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("submitted", "completed", "failed", "rejected",
+                                             "steps", "queued", "running")] + \
+               [(n, ctypes.c_double) for n in ("p50_us", "p99_us", "mean_us", "max_us",
+                                              "req_per_s", "eff_nnz_per_s")] + \
+               [("bytes_in_use", ctypes.c_uint64)]
+
+
+SIGNATURES.update({
+    "systec_serve_create": [ctypes.POINTER(ServeConfig), PP],
+    "systec_serve_register": [P, P, PI64],
+    "systec_serve_unregister": [P, I64],
+    "systec_serve_submit": [P, I64, P, I32, I64, P, I64, PI64],
+    "systec_serve_poll": [P, I64, ctypes.POINTER(ctypes.c_int)],
+    "systec_serve_wait": [P, I64, I64],
+    "systec_serve_get_stats": [P, ctypes.POINTER(ServeStats)],
+    "systec_serve_reset_stats": [P],
+    "systec_serve_now_ns": [],
+    "systec_serve_destroy": [P],
+})
+_RESTYPE = {"systec_last_error": ctypes.c_char_p, "systec_version": ctypes.c_char_p,
+            "systec_serve_now_ns": ctypes.c_int64}
 
 _lib = None
 

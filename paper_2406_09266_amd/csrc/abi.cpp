@@ -113,10 +113,6 @@ LaunchTimer::~LaunchTimer() {
 
 using namespace systec;
 
-struct systec_tensor {
-  systec::Tensor* impl;
-};
-
 extern "C" {
 
 const char* systec_last_error(void) { return g_last_error.c_str(); }

@@ -106,6 +106,7 @@ struct Tensor {
   int32_t* chunk_panel = nullptr;
   int32_t* chunk_tile_begin = nullptr;
   int32_t* chunk_tile_end = nullptr;
+  std::vector<int32_t> h_chunk_panel, h_chunk_tile_begin, h_chunk_tile_end;  // host copies
   // tensor
   int64_t vnnz[5] = {0, 0, 0, 0, 0};
   int32_t* vidx[5][5] = {};
@@ -121,6 +122,38 @@ int launch_ssymv_panel(const Tensor* t, const void* x, systec_dtype xdt, float* 
                        hipStream_t s);
 int launch_mttkrp_views(const Tensor* t, const void* B, systec_dtype bdt, int64_t R, float* C,
                         hipStream_t s);
+
+// ---- serving step (serve_kernel.hip) ----------------------------------------
+// One work item of a serving step: a chunk of a prepared matrix (SSYMV) or a
+// range of one slot view of a prepared tensor (MTTKRP), with the request's
+// input and output.
+struct ServeItem {
+  int32_t kind;   // 0: SSYMV panel chunk, 1: MTTKRP slot-view range
+  int32_t dtype;  // systec_dtype of the input
+  int32_t order;
+  int32_t slot;   // view (MTTKRP)
+  int32_t dim;    // n or I
+  int32_t H;      // panel rows (SSYMV)
+  int32_t R;      // columns (MTTKRP), <= 64
+  int32_t panel;  // (SSYMV)
+  int32_t begin;  // tile range (SSYMV) or entry range (MTTKRP)
+  int32_t end;
+  int32_t pad0, pad1;
+  const void* p[5];  // SSYMV: pcol, prow, pval; MTTKRP: the view's index arrays
+  const float* val;  // MTTKRP: the view's values
+  const void* in;    // x or B
+  float* out;        // y or C
+};
+struct ZeroSeg {
+  float* ptr;
+  int64_t count;
+};
+constexpr int kServeBlock = 512;
+constexpr int kServeLds = 16384 * 4;  // bytes: the row sums of one panel
+// Zeroes the segments and resets the step's work counter, then runs the
+// persistent step kernel over the items (both on stream s).
+int launch_serve_step(const ZeroSeg* d_zero, int nzero, const ServeItem* d_items, int nitems,
+                      int* d_counter, int grid, hipStream_t s);
 
 // ---- multiplicity rule (host and device) ----------------------------------
 // For a sorted tuple of `order` indices whose equality pattern is `mask`
@@ -164,3 +197,8 @@ constexpr CoefTable make_coef_table(int order) {
 }
 
 }  // namespace systec
+
+// The opaque handle of the C ABI.
+struct systec_tensor {
+  systec::Tensor* impl;
+};

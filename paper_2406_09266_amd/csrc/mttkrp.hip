@@ -13,160 +13,53 @@
 // for each slot t that starts a run of equal indices. Each factor row is
 // read once per entry (common tensor access elimination, Sec. 4.2.1).
 //
-// GPU decomposition. A wavefront owns a tile of consecutive entries. It is
-// split into groups of L lanes (L = 8/16/32/64, the smallest power of two
-// >= R, or 64 with column blocks for R > 64); each group walks every
-// (64/L)-th entry of the tile with one lane per output column, so factor-row
-// gathers and output-row updates are contiguous L-wide accesses. Entries are
-// sorted by c1, so slot 1 accumulates in registers across a run of equal c1
-// and is written once per run (the workspace transformation, Sec. 4.2.8);
-// the other run-start slots scatter with FP32 atomics.
+// GPU decomposition (mttkrp_device.h). A wavefront owns a tile of consecutive
+// entries. It is split into groups of L lanes (L = 8/16/32/64, the smallest
+// power of two >= R, or 64 with column blocks for R > 64); each group walks
+// every (64/L)-th entry of the tile with one lane per output column, so
+// factor-row gathers and output-row updates are contiguous L-wide accesses.
+// Entries are sorted by c1, so slot 1 accumulates in registers across a run
+// of equal c1 and is written once per run (the workspace transformation,
+// Sec. 4.2.8); the other run-start slots scatter with FP32 atomics. The
+// prepared form (slot views) has no scattered slot at all.
 #include "common.h"
+#include "mttkrp_device.h"
 
 namespace systec {
-
-__constant__ CoefTable kCoef3 = make_coef_table(3);
-__constant__ CoefTable kCoef4 = make_coef_table(4);
-__constant__ CoefTable kCoef5 = make_coef_table(5);
-
 namespace {
+
+using namespace dev;
 
 constexpr int kWaves = 4;
 constexpr int kBlock = kWave * kWaves;
-constexpr int kTileE = 256;  // entries per wavefront tile
 
-struct IdxPtrs {
-  const int32_t* p[5];
-};
-
-template <int N>
-__device__ __forceinline__ const CoefTable& coef_table();
-template <>
-__device__ __forceinline__ const CoefTable& coef_table<3>() { return kCoef3; }
-template <>
-__device__ __forceinline__ const CoefTable& coef_table<4>() { return kCoef4; }
-template <>
-__device__ __forceinline__ const CoefTable& coef_table<5>() { return kCoef5; }
-
-// Leave-one-out products: loo[t] = prod_{s != t} b[s].
-template <int N>
-__device__ __forceinline__ void leave_one_out(const float (&b)[N], float (&loo)[N]) {
-  float pre[N], suf[N];
-  pre[0] = 1.0f;
-#pragma unroll
-  for (int t = 1; t < N; ++t) pre[t] = (t == 1) ? b[0] : pre[t - 1] * b[t - 1];
-  suf[N - 1] = 1.0f;
-#pragma unroll
-  for (int t = N - 2; t >= 0; --t) suf[t] = (t == N - 2) ? b[N - 1] : suf[t + 1] * b[t + 1];
-#pragma unroll
-  for (int t = 0; t < N; ++t)
-    loo[t] = (t == 0) ? suf[0] : (t == N - 1) ? pre[N - 1] : pre[t] * suf[t];
-}
-
-// kSym: canonical entries of a symmetric tensor (coefficient table, every
-// run-start slot updated). Otherwise: plain entries, only slot 1 is output.
+// One wave per tile of kTileE consecutive canonical entries.
 template <int N, typename BT, int L, bool kSym>
 __global__ __launch_bounds__(kBlock) void mttkrp_tiles_kernel(int nnz, IdxPtrs idx,
                                                             const float* __restrict__ val,
                                                             const BT* __restrict__ B, int ldb,
                                                             float* __restrict__ C, int ldc,
                                                             int col0, int ncols) {
-  constexpr int G = kWave / L;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int g = lane / L;
-  const int cl = lane - g * L;
-  const bool col_ok = cl < ncols;
-  const int col = col0 + (col_ok ? cl : 0);
   const int64_t wave = static_cast<int64_t>(blockIdx.x) * kWaves + threadIdx.x / kWave;
-  const int64_t e_begin = wave * kTileE;
-  if (e_begin >= nnz) return;
-  const int e_end = static_cast<int>(min<int64_t>(nnz, e_begin + kTileE));
-
-  int cur = -1;
-  float acc = 0.0f;
-  for (int e = static_cast<int>(e_begin) + g; e < e_end; e += G) {
-    int c[N];
-#pragma unroll
-    for (int t = 0; t < N; ++t) c[t] = idx.p[t][e];
-    const float v = val[e];
-    float b[N];
-#pragma unroll
-    for (int t = 0; t < N; ++t) b[t] = load_f32(B, static_cast<int64_t>(c[t]) * ldb + col);
-    float loo[N];
-    leave_one_out<N>(b, loo);
-
-    if (c[0] != cur) {
-      if (cur >= 0 && col_ok) atomic_add_noret(C + static_cast<int64_t>(cur) * ldc + col, acc);
-      cur = c[0];
-      acc = 0.0f;
-    }
-    if constexpr (kSym) {
-      int mask = 0;
-#pragma unroll
-      for (int t = 0; t + 1 < N; ++t) mask |= (c[t] == c[t + 1]) ? (1 << t) : 0;
-      const float* coef = coef_table<N>().coef[mask];
-      acc += coef[0] * v * loo[0];
-#pragma unroll
-      for (int t = 1; t < N; ++t) {
-        const float k = coef[t];
-        if (k != 0.0f && col_ok)
-          atomic_add_noret(C + static_cast<int64_t>(c[t]) * ldc + col, k * v * loo[t]);
-      }
-    } else {
-      acc += v * loo[0];
-    }
-  }
-  if (cur >= 0 && col_ok) atomic_add_noret(C + static_cast<int64_t>(cur) * ldc + col, acc);
+  const int64_t e0 = wave * kTileE;
+  if (e0 >= nnz) return;
+  const int e1 = static_cast<int>(min<int64_t>(nnz, e0 + kTileE));
+  mttkrp_canonical_tile<N, BT, L, kSym>(static_cast<int>(e0), e1, idx, val, B, ldb, C, ldc, col0,
+                                        ncols);
 }
 
-// MTTKRP over one slot view of a prepared tensor (see plan.hip): every entry
-// of view t updates C[c_t] with its slot-t coefficient, and the view is sorted
-// by c_t, so all updates are register accumulations written once per run.
+// One wave per tile of kTileE consecutive entries of slot view t.
 template <int N, typename BT, int L>
 __global__ __launch_bounds__(kBlock) void mttkrp_view_kernel(int t, int nnz, IdxPtrs idx,
                                                            const float* __restrict__ val,
                                                            const BT* __restrict__ B, int ldb,
                                                            float* __restrict__ C, int ldc,
                                                            int col0, int ncols) {
-  constexpr int G = kWave / L;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int g = lane / L;
-  const int cl = lane - g * L;
-  const bool col_ok = cl < ncols;
-  const int col = col0 + (col_ok ? cl : 0);
   const int64_t wave = static_cast<int64_t>(blockIdx.x) * kWaves + threadIdx.x / kWave;
-  const int64_t e_begin = wave * kTileE;
-  if (e_begin >= nnz) return;
-  const int e_end = static_cast<int>(min<int64_t>(nnz, e_begin + kTileE));
-
-  int cur = -1;
-  float acc = 0.0f;
-  for (int e = static_cast<int>(e_begin) + g; e < e_end; e += G) {
-    int c[N];
-#pragma unroll
-    for (int s = 0; s < N; ++s) c[s] = idx.p[s][e];
-    const float v = val[e];
-    int mask = 0;
-#pragma unroll
-    for (int s = 0; s + 1 < N; ++s) mask |= (c[s] == c[s + 1]) ? (1 << s) : 0;
-    float prod = coef_table<N>().coef[mask][t] * v;
-    int out = c[0];
-#pragma unroll
-    for (int s = 0; s < N; ++s) {
-      if (s == t) {
-        out = c[s];
-      } else {
-        prod *= load_f32(B, static_cast<int64_t>(c[s]) * ldb + col);
-      }
-    }
-    if (out != cur) {
-      if (cur >= 0 && col_ok) atomic_add_noret(C + static_cast<int64_t>(cur) * ldc + col, acc);
-      cur = out;
-      acc = 0.0f;
-    }
-    acc += prod;
-  }
-  if (cur >= 0 && col_ok) atomic_add_noret(C + static_cast<int64_t>(cur) * ldc + col, acc);
+  const int64_t e0 = wave * kTileE;
+  if (e0 >= nnz) return;
+  const int e1 = static_cast<int>(min<int64_t>(nnz, e0 + kTileE));
+  mttkrp_view_tile<N, BT, L>(t, static_cast<int>(e0), e1, idx, val, B, ldb, C, ldc, col0, ncols);
 }
 
 template <int N, typename BT, int L, bool kSym>

@@ -281,6 +281,9 @@ int tensor_create_csr(int64_t n, int64_t nnz, const int32_t* rowptr, const int32
   }
   t->padded = ppos;
   t->nchunks = static_cast<int>(ch_panel.size());
+  t->h_chunk_panel = ch_panel;
+  t->h_chunk_tile_begin = ch_begin;
+  t->h_chunk_tile_end = ch_end;
   rc = tensor_alloc(t, &t->pcol, ppos);
   if (!rc) rc = tensor_alloc(t, &t->prow, ppos);
   if (!rc) rc = tensor_alloc(t, &t->pval, ppos);

@@ -21,82 +21,16 @@
 // sequentially by row; the wave combines the segments that cross lanes with a
 // DPP segmented scan, so a row spanning a whole tile costs one atomic.
 #include "common.h"
+#include "panel_device.h"
+#include "wave_ops.h"
 
 namespace systec {
 namespace {
 
-constexpr int kV = 8;                 // entries per lane
-constexpr int kTile = kWave * kV;     // entries per wavefront tile
+using namespace dev;
+
 constexpr int kWaves = 4;             // wavefronts per workgroup
 constexpr int kBlock = kWave * kWaves;
-
-// ---- wave-level primitives (DPP; wave64) ----------------------------------
-// DPP controls: row_shr:n = 0x110+n, row_bcast:15 = 0x142, row_bcast:31 = 0x143.
-template <int kCtrl, int kRowMask>
-__device__ __forceinline__ int dpp_i32(int old, int src) {
-  return __builtin_amdgcn_update_dpp(old, src, kCtrl, kRowMask, 0xf, false);
-}
-template <int kCtrl, int kRowMask>
-__device__ __forceinline__ float dpp_f32(float old, float src) {
-  return __int_as_float(
-      __builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(src), kCtrl, kRowMask, 0xf,
-                                  false));
-}
-
-// Inclusive max-scan over the 64 lanes.
-__device__ __forceinline__ int wave_incl_max(int v) {
-  v = max(v, dpp_i32<0x111, 0xf>(INT_MIN, v));
-  v = max(v, dpp_i32<0x112, 0xf>(INT_MIN, v));
-  v = max(v, dpp_i32<0x114, 0xf>(INT_MIN, v));
-  v = max(v, dpp_i32<0x118, 0xf>(INT_MIN, v));
-  v = max(v, dpp_i32<0x142, 0xa>(INT_MIN, v));
-  v = max(v, dpp_i32<0x143, 0xc>(INT_MIN, v));
-  return v;
-}
-
-// Inclusive segmented sum over the 64 lanes; segments are runs of equal keys
-// (keys are nondecreasing across lanes).
-__device__ __forceinline__ float wave_seg_sum(int key, float v) {
-#define SYSTEC_SEG_STEP(CTRL, MASK)                         \
-  {                                                         \
-    const int k2 = dpp_i32<CTRL, MASK>(-2, key);            \
-    const float v2 = dpp_f32<CTRL, MASK>(0.0f, v);          \
-    v += (k2 == key) ? v2 : 0.0f;                           \
-  }
-  SYSTEC_SEG_STEP(0x111, 0xf)
-  SYSTEC_SEG_STEP(0x112, 0xf)
-  SYSTEC_SEG_STEP(0x114, 0xf)
-  SYSTEC_SEG_STEP(0x118, 0xf)
-  SYSTEC_SEG_STEP(0x142, 0xa)
-  SYSTEC_SEG_STEP(0x143, 0xc)
-#undef SYSTEC_SEG_STEP
-  return v;
-}
-
-__device__ __forceinline__ float wave_sum(float v) {
-  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
-  return v;
-}
-
-// Finishes a wave's segmented sums. Each lane has summed its own entries by
-// key (keys nondecreasing across lanes): segments strictly inside the lane are
-// already written; `first_key`/`head_val` is its first segment when the lane
-// holds more than one (nseg >= 2) and `tail_key`/`tail` its last one. The
-// last segments are combined across lanes with a segmented scan; a segment
-// that continues into the next lane is written by the lane where it ends.
-__device__ __forceinline__ void flush_lane_segments(int lane, int first_key, int tail_key,
-                                                    float tail_part, float head_val, int nseg,
-                                                    float* __restrict__ y) {
-  const float tail = wave_seg_sum(tail_key, tail_part);
-  const int prev_key = __shfl_up(tail_key, 1);
-  const float prev_tail = __shfl_up(tail, 1);
-  const int next_first = __shfl_down(first_key, 1);
-  if (nseg >= 2) {
-    const float c = (lane > 0 && prev_key == first_key) ? prev_tail : 0.0f;
-    atomic_add_noret(y + first_key, head_val + c);
-  }
-  if (lane == kWave - 1 || next_first != tail_key) atomic_add_noret(y + tail_key, tail);
-}
 
 // Merge-path split (Merrill & Garland's merge-based CSR decomposition): the
 // rows' end offsets and the entry indices form one sorted sequence of n + nnz
@@ -133,18 +67,6 @@ struct TileLds {
   int col[kTile];
   float val[kTile];
 };
-
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__device__ __forceinline__ void read8(const int* p, int (&o)[kV]) {
-  const int4 a = reinterpret_cast<const int4*>(p)[0], b = reinterpret_cast<const int4*>(p)[1];
-  o[0] = a.x; o[1] = a.y; o[2] = a.z; o[3] = a.w;
-  o[4] = b.x; o[5] = b.y; o[6] = b.z; o[7] = b.w;
-}
 
 // Loads merge-path tile `tile` (items [tile*kTile, (tile+1)*kTile) of the
 // n + nnz sequence): at most kTile rows and kTile entries. Returns false if
@@ -312,10 +234,6 @@ __global__ __launch_bounds__(1024) void reduce_partials_f64(const float* __restr
   }
 }
 
-// SSYMV over a matrix in the panel format (see plan.hip). One workgroup per
-// chunk of one panel: the panel's row sums live in LDS (H floats); the
-// entries arrive sorted by column, so the column-side updates reduce by
-// segments across each lane and wave before their atomic.
 template <typename XT>
 __global__ __launch_bounds__(512) void ssymv_panel_kernel(
     int n, int H, const int32_t* __restrict__ chunk_panel,
@@ -324,52 +242,8 @@ __global__ __launch_bounds__(512) void ssymv_panel_kernel(
     const float* __restrict__ pval, const XT* __restrict__ x, float* __restrict__ y) {
   extern __shared__ float s_rows[];  // the panel's row sums
   const int chunk = blockIdx.x;
-  const int p = chunk_panel[chunk];
-  const int tb = chunk_tile_begin[chunk], te = chunk_tile_end[chunk];
-  const int r0 = p * H;
-  for (int i = threadIdx.x; i < H; i += blockDim.x) s_rows[i] = 0.0f;
-  __syncthreads();
-  const int lane = threadIdx.x & (kWave - 1);
-  const int w = threadIdx.x / kWave;
-  const int nw = blockDim.x / kWave;
-  for (int tile = tb + w; tile < te; tile += nw) {
-    const int64_t base = static_cast<int64_t>(tile) * kTile + lane * kV;
-    int c[kV];
-    read8(pcol + base, c);
-    const int4 rr = *reinterpret_cast<const int4*>(prow + base);
-    const uint16_t ro[kV] = {
-        static_cast<uint16_t>(rr.x & 0xffff), static_cast<uint16_t>(static_cast<uint32_t>(rr.x) >> 16),
-        static_cast<uint16_t>(rr.y & 0xffff), static_cast<uint16_t>(static_cast<uint32_t>(rr.y) >> 16),
-        static_cast<uint16_t>(rr.z & 0xffff), static_cast<uint16_t>(static_cast<uint32_t>(rr.z) >> 16),
-        static_cast<uint16_t>(rr.w & 0xffff), static_cast<uint16_t>(static_cast<uint32_t>(rr.w) >> 16)};
-    const float4 va = reinterpret_cast<const float4*>(pval + base)[0];
-    const float4 vb = reinterpret_cast<const float4*>(pval + base)[1];
-    const float a[kV] = {va.x, va.y, va.z, va.w, vb.x, vb.y, vb.z, vb.w};
-
-    const int first_key = c[0];
-    int cur = c[0];
-    float acc = 0.0f, head_val = 0.0f;
-    int nseg = 1;
-#pragma unroll
-    for (int k = 0; k < kV; ++k) {
-      const int r = r0 + ro[k];
-      if (a[k] != 0.0f) atomicAdd(s_rows + ro[k], a[k] * load_f32(x, c[k]));  // y[i] += a x[j]
-      if (c[k] != cur) {
-        if (nseg == 1) head_val = acc;
-        else atomic_add_noret(y + cur, acc);
-        ++nseg;
-        cur = c[k];
-        acc = 0.0f;
-      }
-      if (c[k] != r) acc += a[k] * load_f32(x, r);  // y[j] += a x[i], j > i
-    }
-    flush_lane_segments(lane, first_key, cur, acc, head_val, nseg, y);
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < H; i += blockDim.x) {
-    const float v = s_rows[i];
-    if (v != 0.0f && r0 + i < n) atomic_add_noret(y + r0 + i, v);
-  }
+  ssymv_panel_chunk<XT>(n, H, chunk_panel[chunk], chunk_tile_begin[chunk], chunk_tile_end[chunk],
+                        pcol, prow, pval, x, y, s_rows);
 }
 
 __global__ void fill_f32_kernel(float* __restrict__ p, int64_t n) {

@@ -275,3 +275,56 @@ def workload(name):
     if name == "mttkrp5":
         return sym_coo(5, 5_000, 5_000_000, 0.05, seed=4, R=16)
     raise KeyError(name)
+
+
+# --------------------------------------------------------------------------
+# Device-side generators (torch on the GPU) for the large serving pool
+# --------------------------------------------------------------------------
+
+def _tgen(seed, device):
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    return g
+
+
+def gpu_ssymv_random(n, avg_degree, seed, device="cuda"):
+    """Upper-triangle CSR on the device: about avg_degree * n / 2 uniformly
+    random edges, mapped to (min, max), duplicates merged; values U(0,1)."""
+    import torch
+    g = _tgen(seed, device)
+    m = max(1, int(round(avg_degree * n / 2)))
+    i = torch.randint(0, n, (m,), generator=g, device=device, dtype=torch.int64)
+    j = torch.randint(0, n, (m,), generator=g, device=device, dtype=torch.int64)
+    keys = torch.unique(torch.minimum(i, j) * n + torch.maximum(i, j))
+    rows, cols = keys // n, keys % n
+    counts = torch.bincount(rows, minlength=n)
+    rowptr = torch.zeros(n + 1, dtype=torch.int64, device=device)
+    rowptr[1:] = torch.cumsum(counts, 0)
+    val = torch.rand(cols.numel(), generator=g, device=device, dtype=torch.float32)
+    return {"n": n, "rowptr": rowptr.to(torch.int32), "col": cols.to(torch.int32), "val": val}
+
+
+def gpu_sym_coo(order, dim, nnz, repeat_frac, seed, device="cuda"):
+    """Canonical COO of a random symmetric tensor on the device: iid uniform
+    index tuples (a fraction repeat_frac made to repeat one index), sorted
+    within each tuple, sorted lexicographically, duplicates removed (so the
+    result can hold slightly fewer than nnz entries). Values N(0,1)."""
+    import torch
+    g = _tgen(seed, device)
+    m = int(nnz * 1.05) + 16
+    t = torch.randint(0, dim, (m, order), generator=g, device=device, dtype=torch.int64)
+    rep = torch.rand(m, generator=g, device=device) < repeat_frac
+    k = torch.randint(0, order - 1, (m,), generator=g, device=device)
+    rows = torch.nonzero(rep).squeeze(1)
+    t[rows, k[rows] + 1] = t[rows, k[rows]]
+    t, _ = torch.sort(t, dim=1)
+    for c in range(order - 1, -1, -1):  # lexicographic: stable sorts, last key first
+        _, p = torch.sort(t[:, c], stable=True)
+        t = t[p]
+    keep = torch.ones(t.shape[0], dtype=torch.bool, device=device)
+    keep[1:] = torch.any(t[1:] != t[:-1], dim=1)
+    t = t[keep][:nnz]
+    val = torch.randn(t.shape[0], generator=g, device=device, dtype=torch.float32)
+    idx = [t[:, c].to(torch.int32).contiguous() for c in range(order)]
+    return {"order": order, "dim": dim, "idx": idx, "val": val}

@@ -1,0 +1,171 @@
+"""GPU tests of the serving runtime: results in a concurrent mix equal the same
+requests served alone and the oracle; admission blocks under a small budget
+and resumes; oversize requests are rejected; requests that arrive while
+others run are admitted and complete."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2406_09266_amd as systec
+from paper_2406_09266_amd import synth
+
+from gpu_util import dev, f32, rel_err
+
+pytestmark = pytest.mark.gpu
+TOL32 = 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    yield
+    torch.cuda.synchronize()
+
+
+def _pool():
+    """A small mixed pool: two matrices and two tensors (orders 3 and 4)."""
+    mats = [synth.ssymv_random_degree(30000, 12, seed=71), synth.ssymv_rmat(scale=15, batch=1 << 17,
+                                                                            seed=72)]
+    tens = [synth.sym_coo(3, 2000, 60000, 0.05, seed=73), synth.sym_coo(4, 500, 40000, 0.05, seed=74)]
+    return mats, tens
+
+
+def _register(srv, mats, tens):
+    ids = []
+    for m in mats:
+        ids.append(srv.register(systec.Tensor.from_csr(dev(m["rowptr"]), dev(m["col"]),
+                                                      dev(m["val"].astype(np.float32)))))
+    for t in tens:
+        ids.append(srv.register(systec.Tensor.from_coo([dev(a) for a in t["idx"]],
+                                                      dev(t["val"].astype(np.float32)), t["dim"])))
+    return ids
+
+
+def _requests(mats, tens, count, seed):
+    """(pool index, input as numpy, R) for `count` requests."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    reqs = []
+    for k in range(count):
+        p = int(rng.integers(0, len(mats) + len(tens)))
+        if p < len(mats):
+            reqs.append((p, synth.dense_uniform(mats[p]["n"], seed=1000 + k), 1))
+        else:
+            t = tens[p - len(mats)]
+            R = int(rng.choice([8, 16, 32]))
+            reqs.append((p, synth.dense_uniform((t["dim"], R), seed=1000 + k), R))
+    return reqs
+
+
+def _submit(srv, ids, mats, tens, req, bf16):
+    import torch
+    p, inp, R = req
+    x = dev(inp.astype(np.float32))
+    if bf16:
+        x = systec.quantize_bf16(x)
+    if p < len(mats):
+        out = torch.empty(mats[p]["n"], device="cuda")
+    else:
+        out = torch.empty((tens[p - len(mats)]["dim"], R), device="cuda")
+    torch.cuda.synchronize()  # inputs ready before the server's stream reads them
+    return srv.submit(ids[p], x, out), out
+
+
+def _oracle(mats, tens, req, bf16):
+    p, inp, R = req
+    ref = oracle.round_bf16(inp.astype(np.float32)) if bf16 else f32(inp)
+    if p < len(mats):
+        m = mats[p]
+        return oracle.ssymv(m["n"], m["rowptr"], m["col"], f32(m["val"]), ref)[0]
+    t = tens[p - len(mats)]
+    return oracle.mttkrp(t["order"], t["dim"], t["idx"].T, f32(t["val"]), ref)[0]
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+def test_mix_equals_alone_and_oracle(bf16):
+    mats, tens = _pool()
+    reqs = _requests(mats, tens, 24, seed=5)
+    with systec.Server(budget_bytes=8 << 30, max_slots=8, step_work_nnz=1 << 17) as srv:
+        ids = _register(srv, mats, tens)
+        # alone: one request at a time
+        alone = []
+        for r in reqs:
+            rid, out = _submit(srv, ids, mats, tens, r, bf16)
+            srv.wait(rid, 60_000_000)
+            alone.append(out.cpu().numpy())
+        # mix: all at once (small step budget: requests share steps)
+        outs = []
+        for r in reqs:
+            outs.append(_submit(srv, ids, mats, tens, r, bf16))
+        for rid, _ in outs:
+            srv.wait(rid, 60_000_000)
+        st = srv.stats()
+    for r, a, (_, o) in zip(reqs, alone, outs):
+        mix = o.cpu().numpy()
+        assert rel_err(mix, a) <= TOL32
+        assert rel_err(mix, _oracle(mats, tens, r, bf16)) <= TOL32
+    assert st["completed"] == 48 and st["failed"] == 0
+    assert st["p99_us"] >= st["p50_us"] > 0
+
+
+def test_small_budget_blocks_and_resumes():
+    import torch
+    m = synth.ssymv_random_degree(200000, 16, seed=81)
+    mats = [m]
+    with systec.Server(budget_bytes=1 << 40, max_slots=4) as probe:
+        _register(probe, mats, [])
+        resident = probe.stats()["bytes_in_use"]
+    one = m["n"] * (4 + 4)  # one FP32 request: input + output
+    reqs = _requests(mats, [], 20, seed=9)
+    xs = [dev(r[1].astype(np.float32)) for r in reqs]
+    ys = [torch.empty(m["n"], device="cuda") for _ in reqs]
+    torch.cuda.synchronize()
+    # room for the tensor and one request at a time
+    with systec.Server(budget_bytes=resident + one + one // 2, max_slots=4,
+                       step_work_nnz=1 << 14) as srv:
+        ids = _register(srv, mats, [])
+        rids = [srv.submit(ids[0], x, y) for x, y in zip(xs, ys)]
+        states = [srv.poll(rid) for rid in rids]
+        assert states.count(srv.RUNNING) <= 1
+        assert srv.QUEUED in states  # the budget holds later requests back
+        for rid in rids:
+            srv.wait(rid, 60_000_000)
+        assert srv.stats()["completed"] == 20
+    for r, y in zip(reqs, ys):
+        assert rel_err(y.cpu().numpy(), _oracle(mats, [], r, False)) <= TOL32
+    # a request that can never fit next to the resident tensor is rejected
+    with systec.Server(budget_bytes=resident + one // 2, max_slots=4) as srv:
+        ids = _register(srv, mats, [])
+        with pytest.raises(systec.SystecError) as e:
+            srv.submit(ids[0], xs[0], ys[0])
+        assert e.value.status_name == "SYSTEC_EBUDGET"
+        assert srv.stats()["rejected"] == 1
+
+
+def test_arrivals_while_running_are_admitted():
+    mats, tens = _pool()
+    reqs = _requests(mats, tens, 40, seed=11)
+    with systec.Server(budget_bytes=8 << 30, max_slots=16, step_work_nnz=1 << 16) as srv:
+        ids = _register(srv, mats, tens)
+        outs = []
+        for k, r in enumerate(reqs):
+            outs.append(_submit(srv, ids, mats, tens, r, True))
+            if k == 5:
+                assert any(srv.poll(rid) != srv.QUEUED for rid, _ in outs[:5])
+        for rid, _ in outs:
+            srv.wait(rid, 60_000_000)
+        st = srv.stats()
+    assert st["completed"] == 40 and st["steps"] >= 2
+    for r, (_, o) in zip(reqs, outs):
+        assert rel_err(o.cpu().numpy(), _oracle(mats, tens, r, True)) <= TOL32
+
+
+def test_unknown_ids_and_timeout():
+    with systec.Server(budget_bytes=1 << 30) as srv:
+        with pytest.raises(systec.SystecError) as e:
+            srv.poll(12345)
+        assert e.value.status_name == "SYSTEC_ENOTFOUND"
+        with pytest.raises(systec.SystecError) as e:
+            srv.wait(12345, 10)
+        assert e.value.status_name == "SYSTEC_ENOTFOUND"
