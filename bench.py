@@ -46,6 +46,8 @@ def parse():
                     help="served_mix: resident tensors per kind (SSYMV, 3-D, 4-D)")
     ap.add_argument("--requests", type=int, default=1000,
                     help="served_mix: requests per Poisson run")
+    ap.add_argument("--step-work", type=int, default=1 << 25,
+                    help="served_mix: stored entries per serving step")
     ap.add_argument("--loads", default="0.5,0.8,0.95",
                     help="served_mix: offered loads as fractions of saturation")
     ap.add_argument("--form", default="bf16", choices=["f32", "bf16"],
@@ -186,13 +188,18 @@ def main():
                "accumulate": "f32"}
 
     if a.copy_calibration:
+        # a plain device copy of known size, its source pushed out of the
+        # last-level cache first, so that FETCH_SIZE/WRITE_SIZE of its
+        # dispatch can be compared with the bytes it must move
         src = torch.empty(a.copy_calibration << 18, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         src.fill_(1.0)
+        flush = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        flush.fill_(0.0)
         torch.cuda.synchronize()
         dst.copy_(src)
         torch.cuda.synchronize()
-        del src, dst
+        del src, dst, flush
 
     step, other = (prepared, oneshot) if a.path == "prepared" else (oneshot, prepared)
     cfg["path"] = a.path
@@ -355,7 +362,7 @@ def served_mix(a, torch, systec, synth, dev):
         return reqs
 
     budget = 200 << 30
-    srv = systec.Server(budget_bytes=budget, max_slots=32, step_work_nnz=1 << 24)
+    srv = systec.Server(budget_bytes=budget, max_slots=32, step_work_nnz=a.step_work)
     ids = [srv.register(t) for t in served_t]
 
     def out_for(p, R):
@@ -410,6 +417,7 @@ def served_mix(a, torch, systec, synth, dev):
     result = {"metric": "served p50/p99 latency (us) and throughput, BF16 continuous batching "
                         "vs plain FP32 one request at a time",
               "workload": "served_mix", "n_gpus": 1, "data": "synthetic (device generators)",
+              "server": {"max_slots": 32, "step_work_nnz": a.step_work},
               "pool": {"tensors": len(pool), "per_kind": K, "resident_bytes": resident,
                        "budget_bytes": budget, "effective_nnz_total": int(sum(eff)),
                        "generate_s": round(t_gen, 2), "prepare_s": round(t_prep, 2)},

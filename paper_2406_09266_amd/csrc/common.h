@@ -148,12 +148,15 @@ struct ZeroSeg {
   float* ptr;
   int64_t count;
 };
-constexpr int kServeBlock = 512;
-constexpr int kServeLds = 16384 * 4;  // bytes: the row sums of one panel
-// Zeroes the segments and resets the step's work counter, then runs the
-// persistent step kernel over the items (both on stream s).
-int launch_serve_step(const ZeroSeg* d_zero, int nzero, const ServeItem* d_items, int nitems,
-                      int* d_counter, int grid, hipStream_t s);
+constexpr int kServeBlock = 512;       // SSYMV step kernel
+constexpr int kServeMttkrpBlock = 256; // MTTKRP step kernel
+constexpr int kServeLds = 16384 * 4;   // bytes: the row sums of one panel
+// Zeroes the segments and resets the step's four work counters.
+int launch_serve_zero(const ZeroSeg* d_zero, int nzero, int* d_counters, hipStream_t s);
+// Runs a persistent step kernel over items of one kind (0: SSYMV; 3, 4, 5:
+// MTTKRP of that order).
+int launch_serve_items(int kind, const ServeItem* d_items, int nitems, int* d_counter, int grid,
+                       hipStream_t s);
 
 // ---- multiplicity rule (host and device) ----------------------------------
 // For a sorted tuple of `order` indices whose equality pattern is `mask`

@@ -155,6 +155,14 @@ __device__ __forceinline__ void mttkrp_view_tile(int t, int e0, int e1, const Id
       for (int s = 0; s < N; ++s) c[u][s] = ok[u] ? idx.p[s][e] : 0;
       v[u] = ok[u] ? val[e] : 0.0f;
     }
+    // All N factor rows are gathered unconditionally (the slot-t row is the
+    // output row: sorted, so it is nearly always cached); a runtime test on
+    // the slot would split the gathers into dependent branches.
+    float b[kUnroll][N];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+      for (int s = 0; s < N; ++s) b[u][s] = load_f32(B, static_cast<int64_t>(c[u][s]) * ldb + lc.col);
     float prod[kUnroll];
     int out[kUnroll];
 #pragma unroll
@@ -163,8 +171,8 @@ __device__ __forceinline__ void mttkrp_view_tile(int t, int e0, int e1, const Id
       int o = c[u][0];
 #pragma unroll
       for (int s = 0; s < N; ++s) {
-        if (s == t) o = c[u][s];
-        else p *= load_f32(B, static_cast<int64_t>(c[u][s]) * ldb + lc.col);
+        o = (s == t) ? c[u][s] : o;
+        p *= (s == t) ? 1.0f : b[u][s];
       }
       prod[u] = p;
       out[u] = o;

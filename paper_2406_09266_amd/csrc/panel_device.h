@@ -10,9 +10,12 @@ namespace dev {
 
 // SSYMV over one chunk (tiles [tb, te) of panel p) of a matrix in the panel
 // format (see plan.hip), by the whole workgroup, which it synchronizes. The
-// panel's row sums live in LDS (s_rows, H floats); the entries arrive sorted
-// by column, so the column-side updates reduce by segments across each lane
-// and wave before their atomic.
+// panel's row sums live in LDS (s_rows, H floats). The entries arrive sorted
+// by column and are taken lane-strided (step k of a wave holds 64 consecutive
+// entries), so the column-side updates y[j] += a x[i] reduce across the wave
+// by a segmented scan per step, and the segment totals leave in one atomic
+// instruction whose lanes hold consecutive columns (coalesced into few cache
+// lines). A segment running past the step carries into the next step.
 template <typename XT>
 __device__ __forceinline__ void ssymv_panel_chunk(int n, int H, int p, int tb, int te,
                                                   const int32_t* __restrict__ pcol,
@@ -27,37 +30,39 @@ __device__ __forceinline__ void ssymv_panel_chunk(int n, int H, int p, int tb, i
   const int w = threadIdx.x / kWave;
   const int nw = blockDim.x / kWave;
   for (int tile = tb + w; tile < te; tile += nw) {
-    const int64_t base = static_cast<int64_t>(tile) * kTile + lane * kV;
+    const int64_t base = static_cast<int64_t>(tile) * kTile + lane;
     int c[kV];
-    read8(pcol + base, c);
-    const int4 rr = *reinterpret_cast<const int4*>(prow + base);
-    const uint16_t ro[kV] = {
-        static_cast<uint16_t>(rr.x & 0xffff), static_cast<uint16_t>(static_cast<uint32_t>(rr.x) >> 16),
-        static_cast<uint16_t>(rr.y & 0xffff), static_cast<uint16_t>(static_cast<uint32_t>(rr.y) >> 16),
-        static_cast<uint16_t>(rr.z & 0xffff), static_cast<uint16_t>(static_cast<uint32_t>(rr.z) >> 16),
-        static_cast<uint16_t>(rr.w & 0xffff), static_cast<uint16_t>(static_cast<uint32_t>(rr.w) >> 16)};
-    const float4 va = reinterpret_cast<const float4*>(pval + base)[0];
-    const float4 vb = reinterpret_cast<const float4*>(pval + base)[1];
-    const float a[kV] = {va.x, va.y, va.z, va.w, vb.x, vb.y, vb.z, vb.w};
-
-    const int first_key = c[0];
-    int cur = c[0];
-    float acc = 0.0f, head_val = 0.0f;
-    int nseg = 1;
+    int ro[kV];
+    float a[kV];
+#pragma unroll
+    for (int k = 0; k < kV; ++k) {  // coalesced: a step reads 64 consecutive entries
+      c[k] = pcol[base + k * kWave];
+      ro[k] = prow[base + k * kWave];
+      a[k] = pval[base + k * kWave];
+    }
+    int carry_key = -1;
+    float carry = 0.0f;
 #pragma unroll
     for (int k = 0; k < kV; ++k) {
       const int r = r0 + ro[k];
       if (a[k] != 0.0f) atomicAdd(s_rows + ro[k], a[k] * load_f32(x, c[k]));  // y[i] += a x[j]
-      if (c[k] != cur) {
-        if (nseg == 1) head_val = acc;
-        else atomic_add_noret(y + cur, acc);
-        ++nseg;
-        cur = c[k];
-        acc = 0.0f;
+      const float v = (c[k] != r) ? a[k] * load_f32(x, r) : 0.0f;           // y[j] += a x[i]
+      // the previous step's last segment either continues in lane 0 here or
+      // is complete and must be written now
+      if (__shfl(c[k], 0) != carry_key) {
+        if (lane == 0 && carry != 0.0f) atomic_add_noret(y + carry_key, carry);
+        carry_key = -1;
+        carry = 0.0f;
       }
-      if (c[k] != r) acc += a[k] * load_f32(x, r);  // y[j] += a x[i], j > i
+      float seg = wave_seg_sum(c[k], v);
+      if (c[k] == carry_key) seg += carry;  // only lanes of the first segment match
+      const int next_key = __shfl_down(c[k], 1);
+      const bool ends = lane != kWave - 1 && next_key != c[k];
+      if (ends && seg != 0.0f) atomic_add_noret(y + c[k], seg);
+      carry_key = __shfl(c[k], kWave - 1);
+      carry = __shfl(seg, kWave - 1);
     }
-    flush_lane_segments(lane, first_key, cur, acc, head_val, nseg, y);
+    if (lane == 0 && carry != 0.0f) atomic_add_noret(y + carry_key, carry);
   }
   __syncthreads();
   for (int i = threadIdx.x; i < H; i += blockDim.x) {

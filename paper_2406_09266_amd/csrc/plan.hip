@@ -63,13 +63,23 @@ __global__ void panel_keys_kernel(int nnz, int hbits, const int32_t* __restrict_
   }
 }
 
-__global__ void panel_count_kernel(int nnz, int hbits, const unsigned long long* __restrict__ keys,
+// Entries per panel from the sorted keys: panel p starts at the first key
+// whose panel field is >= p (binary search; no atomics on hot counters).
+__global__ void panel_count_kernel(int nnz, int hbits, int npanels,
+                                   const unsigned long long* __restrict__ keys,
                                    int32_t* __restrict__ counts) {
   const int stride = gridDim.x * blockDim.x;
-  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < nnz; s += stride) {
-    const int p = static_cast<int>(keys[s] >> (31 + hbits));
-    atomicAdd(&counts[p], 1);
-  }
+  auto first_of = [&](long long p) {
+    int lo = 0, hi = nnz;  // first s with panel(keys[s]) >= p
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (static_cast<long long>(keys[mid] >> (31 + hbits)) < p) lo = mid + 1;
+      else hi = mid;
+    }
+    return lo;
+  };
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < npanels; p += stride)
+    counts[p] = first_of(p + 1) - first_of(p);
 }
 
 __global__ void panel_scatter_kernel(int nnz, int hbits, const unsigned long long* __restrict__ keys,
@@ -244,7 +254,7 @@ int tensor_create_csr(int64_t n, int64_t nnz, const int32_t* rowptr, const int32
     rc = check_launch("panel key kernels");
     if (!rc) rc = radix_sort_pairs(kin, kout, vin, vout, nz, 31 + hbits + bits_for(P + 1), s);
     if (!rc) {
-      panel_count_kernel<<<grid_for(nnz, 256), 256, 0, s>>>(nz, hbits, kout, counts);
+      panel_count_kernel<<<grid_for(P, 256), 256, 0, s>>>(nz, hbits, P, kout, counts);
       rc = check_launch("panel count kernel");
     }
     if (!rc)

@@ -1,10 +1,13 @@
 // Serving runtime: the GPU executor behind the scheduler core (serve_core.h)
 // and the systec_serve_* entry points.
 //
-// Each step is one H2D copy of its work items (pinned ring buffer), one zero
-// kernel for the outputs of newly admitted requests, one persistent step
-// kernel, and one event; up to two steps are in flight, so the host builds
-// step s+1 while step s runs. All work of a server runs on its own stream.
+// Each step copies its work items from a ring of pinned host buffers to the
+// device, then issues one zero kernel for the outputs of newly admitted
+// requests and the persistent step kernels (SSYMV items with the panel row
+// sums in LDS on the first stream; MTTKRP items, one kernel per tensor
+// order, each on a stream of its own), every stream closed by an event. Up to
+// three steps are in flight, so the host builds the next step while others
+// run.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -18,10 +21,12 @@
 namespace systec {
 namespace {
 
-constexpr int kRing = 4;                   // step buffers (>= steps in flight)
+constexpr int kRing = 4;                   // step buffers (> steps in flight)
 constexpr int kMaxItems = 1 << 16;         // work items per step
-constexpr int kMaxZero = 4096;             // newly admitted requests per step
-constexpr int64_t kViewUnit = 16 * 256;    // entries per MTTKRP work unit
+constexpr int kMaxZero = 1 << 16;          // output pieces to zero per step
+constexpr int64_t kZeroPiece = 16384;      // floats per zeroed piece
+constexpr int64_t kViewUnit = 64 * 256;    // entries per MTTKRP work unit
+constexpr int kSsymvUnitTiles = 64;        // panel tiles per SSYMV work unit
 
 class GpuExecutor {
  public:
@@ -29,16 +34,23 @@ class GpuExecutor {
     device_ = device;
     hipError_t e = hipSetDevice(device);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking);
+    for (int k = 0; k < 3 && e == hipSuccess; ++k)
+      e = hipStreamCreateWithFlags(&mstream_[k], hipStreamNonBlocking);
     int cus = 0;
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
-    grid_ = std::max(1, cus) * 2;  // two 512-thread workgroups (64 KiB LDS each) per CU
+    grid_ = std::max(1, cus) * 2;   // SSYMV: two 512-thread workgroups (64 KiB LDS each) per CU
+    grid2_ = std::max(1, cus) * 8;  // MTTKRP: eight 256-thread workgroups per CU
     for (int i = 0; i < kRing && e == hipSuccess; ++i) {
       e = hipHostMalloc(reinterpret_cast<void**>(&h_items_[i]), kMaxItems * sizeof(ServeItem));
-      if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&h_zero_[i]), kMaxZero * sizeof(ZeroSeg));
+      if (e == hipSuccess)
+        e = hipHostMalloc(reinterpret_cast<void**>(&h_zero_[i]), kMaxZero * sizeof(ZeroSeg));
       if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&d_items_[i]), kMaxItems * sizeof(ServeItem));
       if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&d_zero_[i]), kMaxZero * sizeof(ZeroSeg));
-      if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&d_counter_[i]), sizeof(int));
+      if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&d_counter_[i]), 4 * sizeof(int));
       if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_[i], hipEventDisableTiming);
+      for (int k = 0; k < 3 && e == hipSuccess; ++k)
+        e = hipEventCreateWithFlags(&mev_[i][k], hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&evz_[i], hipEventDisableTiming);
     }
     if (e != hipSuccess) {
       *err = std::string("serving executor init: ") + hipGetErrorString(e);
@@ -49,6 +61,8 @@ class GpuExecutor {
 
   ~GpuExecutor() {
     if (stream_) (void)hipStreamSynchronize(stream_);
+    for (hipStream_t ms : mstream_)
+      if (ms) (void)hipStreamSynchronize(ms);
     for (int i = 0; i < kRing; ++i) {
       if (h_items_[i]) (void)hipHostFree(h_items_[i]);
       if (h_zero_[i]) (void)hipHostFree(h_zero_[i]);
@@ -56,8 +70,13 @@ class GpuExecutor {
       if (d_zero_[i]) (void)hipFree(d_zero_[i]);
       if (d_counter_[i]) (void)hipFree(d_counter_[i]);
       if (ev_[i]) (void)hipEventDestroy(ev_[i]);
+      for (hipEvent_t me : mev_[i])
+        if (me) (void)hipEventDestroy(me);
+      if (evz_[i]) (void)hipEventDestroy(evz_[i]);
     }
     if (stream_) (void)hipStreamDestroy(stream_);
+    for (hipStream_t ms : mstream_)
+      if (ms) (void)hipStreamDestroy(ms);
   }
 
   uint64_t request_bytes(const serve::TensorEntry& t, int dtype, int64_t R) const {
@@ -67,15 +86,18 @@ class GpuExecutor {
   }
 
   int launch(const serve::Plan& plan, std::string* err) {
-    if (plan.items.size() > static_cast<size_t>(kMaxItems) ||
-        plan.zero.size() > static_cast<size_t>(kMaxZero)) {
+    size_t pieces = 0;
+    for (const serve::Request* r : plan.zero)
+      pieces += (r->tensor->dim * (r->tensor->kind == 0 ? 1 : r->R) + kZeroPiece - 1) / kZeroPiece;
+    if (plan.items.size() > static_cast<size_t>(kMaxItems) || pieces > static_cast<size_t>(kMaxZero)) {
       *err = "serving step too large for the executor's buffers";
       return serve::kEinval;
     }
     (void)hipSetDevice(device_);
     const int slot = static_cast<int>(plan.step_id % kRing);
-    // the slot's previous step has completed (at most kRing-2 steps in flight)
-    ServeItem* hi = h_items_[slot];
+    // the slot's previous step has completed (fewer than kRing steps in flight)
+    // items grouped by kernel: SSYMV, then MTTKRP of order 3, 4, 5
+    std::vector<ServeItem> groups[4];
     for (size_t k = 0; k < plan.items.size(); ++k) {
       const serve::PlanItem& pi = plan.items[k];
       const Tensor* t = static_cast<const Tensor*>(pi.tensor->payload);
@@ -95,6 +117,7 @@ class GpuExecutor {
         it.p[0] = t->pcol;
         it.p[1] = t->prow;
         it.p[2] = t->pval;
+        groups[0].push_back(it);
       } else {
         it.kind = 1;
         it.R = static_cast<int32_t>(pi.req->R);
@@ -103,18 +126,27 @@ class GpuExecutor {
         it.end = u.c;
         for (int q = 0; q < t->order; ++q) it.p[q] = t->vidx[u.a][q];
         it.val = t->vval[u.a];
+        groups[t->order - 2].push_back(it);
       }
-      hi[k] = it;
+    }
+    ServeItem* hi = h_items_[slot];
+    int offs[4], cnt[4], total = 0;
+    for (int g = 0; g < 4; ++g) {
+      offs[g] = total;
+      cnt[g] = static_cast<int>(groups[g].size());
+      std::copy(groups[g].begin(), groups[g].end(), hi + total);
+      total += cnt[g];
     }
     ZeroSeg* hz = h_zero_[slot];
-    for (size_t k = 0; k < plan.zero.size(); ++k) {
-      const serve::Request* r = plan.zero[k];
-      const int64_t cols = r->tensor->kind == 0 ? 1 : r->R;
-      hz[k] = ZeroSeg{r->out, r->tensor->dim * cols};
+    int nz = 0;
+    for (const serve::Request* r : plan.zero) {
+      const int64_t count = r->tensor->dim * (r->tensor->kind == 0 ? 1 : r->R);
+      for (int64_t o = 0; o < count; o += kZeroPiece)
+        hz[nz++] = ZeroSeg{r->out + o, std::min(kZeroPiece, count - o)};
     }
-    const int ni = static_cast<int>(plan.items.size()), nz = static_cast<int>(plan.zero.size());
     hipError_t e = hipSuccess;
-    if (ni) e = hipMemcpyAsync(d_items_[slot], hi, ni * sizeof(ServeItem), hipMemcpyHostToDevice, stream_);
+    if (total)
+      e = hipMemcpyAsync(d_items_[slot], hi, total * sizeof(ServeItem), hipMemcpyHostToDevice, stream_);
     if (e == hipSuccess && nz)
       e = hipMemcpyAsync(d_zero_[slot], hz, nz * sizeof(ZeroSeg), hipMemcpyHostToDevice, stream_);
     if (e != hipSuccess) {
@@ -124,8 +156,22 @@ class GpuExecutor {
     int rc;
     {
       LaunchTimer timer(stream_);
-      rc = launch_serve_step(d_zero_[slot], nz, d_items_[slot], ni, d_counter_[slot],
-                             std::min(grid_, std::max(1, ni)), stream_);
+      // copies and zeroing on the first stream; everything else after them
+      rc = launch_serve_zero(d_zero_[slot], nz, d_counter_[slot], stream_);
+      if (!rc) rc = check_hip(hipEventRecord(evz_[slot], stream_), "hipEventRecord");
+      // MTTKRP items of order 3, 4, 5 on their own streams, so that the
+      // persistent kernels of a step overlap instead of draining one by one
+      for (int g = 1; g < 4 && !rc; ++g) {
+        hipStream_t ms = mstream_[g - 1];
+        rc = check_hip(hipStreamWaitEvent(ms, evz_[slot], 0), "hipStreamWaitEvent");
+        if (!rc)
+          rc = launch_serve_items(g + 2, d_items_[slot] + offs[g], cnt[g], d_counter_[slot] + g,
+                                  std::min(grid2_, std::max(1, cnt[g])), ms);
+        if (!rc) rc = check_hip(hipEventRecord(mev_[slot][g - 1], ms), "hipEventRecord");
+      }
+      if (!rc)
+        rc = launch_serve_items(0, d_items_[slot], cnt[0], d_counter_[slot],
+                                std::min(grid_, std::max(1, cnt[0])), stream_);
     }
     if (rc) {
       *err = systec_last_error();
@@ -142,11 +188,15 @@ class GpuExecutor {
 
   int query(int64_t step_id, std::string* err) {
     const int slot = static_cast<int>(step_id % kRing);
-    const hipError_t e = hipEventQuery(ev_[slot]);
-    if (e == hipSuccess) return 1;
-    if (e == hipErrorNotReady) return 0;
-    *err = std::string("serving step failed: ") + hipGetErrorString(e);
-    return -1;
+    for (hipEvent_t ev : {ev_[slot], mev_[slot][0], mev_[slot][1], mev_[slot][2]}) {
+      const hipError_t e = hipEventQuery(ev);
+      if (e == hipErrorNotReady) return 0;
+      if (e != hipSuccess) {
+        *err = std::string("serving step failed: ") + hipGetErrorString(e);
+        return -1;
+      }
+    }
+    return 1;
   }
 
   void release(serve::TensorEntry& t) {
@@ -158,28 +208,32 @@ class GpuExecutor {
 
  private:
   int device_ = 0;
-  int grid_ = 512;
+  int grid_ = 512, grid2_ = 2048;
   hipStream_t stream_ = nullptr;
+  hipStream_t mstream_[3] = {nullptr, nullptr, nullptr};
   ServeItem* h_items_[kRing] = {};
   ZeroSeg* h_zero_[kRing] = {};
   ServeItem* d_items_[kRing] = {};
   ZeroSeg* d_zero_[kRing] = {};
   int* d_counter_[kRing] = {};
-  hipEvent_t ev_[kRing] = {};
+  hipEvent_t ev_[kRing] = {}, evz_[kRing] = {};
+  hipEvent_t mev_[kRing][3] = {};
   int64_t slot_step_[kRing] = {-1, -1, -1, -1};
 };
 
 // Work units of a prepared operand: SSYMV chunks, MTTKRP view ranges.
 void make_units(const Tensor* t, std::vector<serve::Unit>* units) {
   if (t->kind == 0) {
-    for (int c = 0; c < t->nchunks; ++c) {
-      serve::Unit u;
-      u.a = t->h_chunk_panel[c];
-      u.b = t->h_chunk_tile_begin[c];
-      u.c = t->h_chunk_tile_end[c];
-      u.cost = static_cast<int64_t>(u.c - u.b) * kPanelTile;
-      units->push_back(u);
-    }
+    // the prepared chunks, cut into pieces of at most kSsymvUnitTiles tiles
+    for (int c = 0; c < t->nchunks; ++c)
+      for (int b = t->h_chunk_tile_begin[c]; b < t->h_chunk_tile_end[c]; b += kSsymvUnitTiles) {
+        serve::Unit u;
+        u.a = t->h_chunk_panel[c];
+        u.b = b;
+        u.c = std::min(t->h_chunk_tile_end[c], b + kSsymvUnitTiles);
+        u.cost = static_cast<int64_t>(u.c - u.b) * kPanelTile;
+        units->push_back(u);
+      }
   } else {
     for (int v = 0; v < t->order; ++v)
       for (int64_t e = 0; e < t->vnnz[v]; e += kViewUnit) {
@@ -226,7 +280,7 @@ int systec_serve_create(const systec_serve_config* cfg, systec_server** out) {
   c.max_slots = cfg->max_slots;
   c.step_work = cfg->step_work_nnz;
   c.max_queue = cfg->max_queue > 0 ? cfg->max_queue : (1 << 20);
-  c.max_inflight = 2;
+  c.max_inflight = 3;
   s->sched.reset(new serve::Scheduler<GpuExecutor>(c, *s->exec));
   *out = s;
   return SYSTEC_OK;

@@ -9,9 +9,10 @@
 // Requests are admitted in arrival order (FIFO, no overtaking) while a slot
 // is free and the budget allows; a request that could never fit returns
 // SYSTEC_EBUDGET at submit. Each step takes work units (chunks of the
-// prepared operand) round-robin from every admitted request, up to a work
-// budget in entries, and hands them to the executor as one launch; requests
-// admitted while a step runs join the next one (continuous batching). A
+// prepared operand) from the admitted requests, up to a work budget in
+// entries (half shared round-robin, half in admission order), and hands them
+// to the executor as one launch; requests admitted while a step runs join the
+// next one (continuous batching). A
 // request retires when the step holding its last unit has completed; its
 // latency runs from its arrival to that moment, queueing included.
 #pragma once
@@ -55,7 +56,7 @@ struct Config {
   int max_slots = 16;
   int64_t step_work = 1 << 24;  // entries per step
   int max_queue = 1 << 20;
-  int max_inflight = 2;         // steps in flight (build step s+1 while s runs)
+  int max_inflight = 3;         // steps in flight (build step s+1 while s runs)
 };
 
 // One schedulable piece of a registered tensor (opaque to the core).
@@ -317,31 +318,39 @@ class Scheduler {
     }
   }
 
-  // Round-robin over active requests until the step's work budget is used.
+  // Fills a step. Half of the work budget is shared round-robin among the
+  // running requests (a small request finishes within its share, so it is
+  // not stuck behind large ones); the rest goes to the running requests in
+  // admission order (a large request keeps most of the device, as it would
+  // alone). Every running request with work left gets at least one unit.
   void fill_locked(Plan& plan, std::vector<std::shared_ptr<Request>>& touched) {
     int64_t budget = cfg_.step_work;
-    bool progress = true;
-    while (budget > 0 && progress) {
-      progress = false;
-      const int64_t live = std::max<int64_t>(1, static_cast<int64_t>(active_.size()));
-      const int64_t share = std::max<int64_t>(1, budget / live);
-      for (auto& r : active_) {
-        const auto& units = r->tensor->units;
-        int64_t got = 0;
-        while (r->next_unit < units.size() && got < share && budget > 0) {
-          const Unit& u = units[r->next_unit];
-          plan.items.push_back(PlanItem{r->tensor.get(), &u, r.get()});
-          got += u.cost;
-          budget -= u.cost;
-          ++r->next_unit;
-          progress = true;
-        }
-        if (got > 0 || (r->next_unit == units.size() && r->last_step < 0)) {
-          if (std::find(touched.begin(), touched.end(), r) == touched.end()) touched.push_back(r);
-        }
-        if (r->next_unit == units.size() && r->last_step < 0) r->last_step = plan.step_id;
-        if (budget <= 0) break;
+    auto take = [&](const std::shared_ptr<Request>& r, int64_t limit) {
+      const auto& units = r->tensor->units;
+      int64_t got = 0;
+      while (r->next_unit < units.size() && (got == 0 || got < limit) && budget > 0) {
+        const Unit& u = units[r->next_unit];
+        plan.items.push_back(PlanItem{r->tensor.get(), &u, r.get()});
+        got += u.cost;
+        budget -= u.cost;
+        ++r->next_unit;
       }
+      if (got > 0 && std::find(touched.begin(), touched.end(), r) == touched.end())
+        touched.push_back(r);
+      if (r->next_unit == units.size() && r->last_step < 0) {
+        r->last_step = plan.step_id;
+        if (std::find(touched.begin(), touched.end(), r) == touched.end()) touched.push_back(r);
+      }
+    };
+    const int64_t live = std::max<int64_t>(1, static_cast<int64_t>(active_.size()));
+    const int64_t share = std::max<int64_t>(1, cfg_.step_work / (2 * live));
+    for (auto& r : active_) {
+      if (budget <= 0) break;
+      take(r, share);
+    }
+    for (auto& r : active_) {
+      if (budget <= 0) break;
+      take(r, budget);
     }
     // requests whose operand has no units at all finish with this step
     for (auto& r : active_)
