@@ -116,8 +116,8 @@ def main():
     a = parse()
     if a.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; "
-                          f"--gpus {a.gpus} is not supported (multi-GPU sharding is a design "
-                          "note only, see DESIGN.md)"}))
+                          f"--gpus {a.gpus} is not supported (sharding across GPUs is not "
+                          "part of this benchmark)"}))
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():
@@ -158,7 +158,7 @@ def main():
         t_prep = time.perf_counter() - t_prep
         prepared = lambda: A.ssymv(x, out=y)  # noqa: E731
         kernel_key = "ssymv_panel" if a.path == "prepared" else "ssymv"
-        kernel_src = ("ssymv.hip", "plan.hip")
+        kernel_src = ("ssymv.hip", "panel_device.h", "wave_ops.h", "plan.hip")
         cfg = {"workload": a.workload, "n": n, "stored_nnz": U, "effective_nnz": eff,
                "diagonal_nnz": hist[1], "x_storage": a.form, "accumulate": "f32"}
     else:
@@ -182,7 +182,7 @@ def main():
         t_prep = time.perf_counter() - t_prep
         prepared = lambda: T.mttkrp(B, out=C)  # noqa: E731
         kernel_key = f"mttkrp{order}_views" if a.path == "prepared" else f"mttkrp{order}"
-        kernel_src = ("mttkrp.hip", "plan.hip")
+        kernel_src = ("mttkrp.hip", "mttkrp_device.h", "plan.hip")
         cfg = {"workload": a.workload, "order": order, "I": I, "R": R, "stored_nnz": nnz,
                "effective_nnz": eff, "pattern_hist": hist, "B_storage": a.form,
                "accumulate": "f32"}
