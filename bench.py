@@ -50,6 +50,9 @@ def parse():
                     help="served_mix: stored entries per serving step")
     ap.add_argument("--loads", default="0.5,0.8,0.95",
                     help="served_mix: offered loads as fractions of saturation")
+    ap.add_argument("--algo", default="auto", choices=["auto", "views", "atomic", "lds"],
+                    help="MTTKRP: how non-leading-slot updates are resolved (auto: the "
+                         "library's choice for the shape)")
     ap.add_argument("--form", default="bf16", choices=["f32", "bf16"],
                     help="storage of x / B (arithmetic is FP32 either way)")
     ap.add_argument("--path", default="prepared", choices=["prepared", "oneshot"],
@@ -176,13 +179,19 @@ def main():
         # index need not be streamed): pointer + other indices + values +
         # factor read once + output written once
         b_alg = 4 * (I + 1) + nnz * (4 * (order - 1) + 4) + I * R * sb + 4 * I * R
-        oneshot = lambda: systec.mttkrp(idx, val, B, out=C)  # noqa: E731
+        algo = a.algo
+        if algo == "auto":
+            algo = systec.mttkrp_choose(I, R, a.form == "bf16", a.path == "prepared")
+        oneshot_algo = "atomic"
+        oneshot = lambda: systec.mttkrp(idx, val, B, out=C, algo=oneshot_algo)  # noqa: E731
         t_prep = time.perf_counter()
         T = systec.Tensor.from_coo(idx, val, I)
         t_prep = time.perf_counter() - t_prep
-        prepared = lambda: T.mttkrp(B, out=C)  # noqa: E731
-        kernel_key = f"mttkrp{order}_views" if a.path == "prepared" else f"mttkrp{order}"
-        kernel_src = ("mttkrp.hip", "mttkrp_device.h", "plan.hip")
+        prepared = lambda: T.mttkrp(B, out=C, algo=algo)  # noqa: E731
+        kernel_key = f"mttkrp{order}_{algo}" + ("" if a.path == "prepared" else "_oneshot")
+        kernel_src = {"views": ("mttkrp.hip", "mttkrp_device.h", "plan.hip"),
+                      "atomic": ("mttkrp.hip", "mttkrp_device.h"),
+                      "lds": ("mttkrp_lds.hip", "mttkrp_device.h", "plan.hip")}[algo]
         cfg = {"workload": a.workload, "order": order, "I": I, "R": R, "stored_nnz": nnz,
                "effective_nnz": eff, "pattern_hist": hist, "B_storage": a.form,
                "accumulate": "f32"}
@@ -225,6 +234,18 @@ def main():
                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                        "traffic": traffic, "kernel": kernel_key, "kernel_ms": k_ms,
                        "kernel_source_hash": h}
+
+    # ---- every MTTKRP algorithm on the same prepared tensor ----
+    if not a.workload.startswith("ssymv"):
+        out["algos"] = {}
+        for name in ("views", "atomic", "lds"):
+            try:
+                fn = lambda: T.mttkrp(B, out=C, algo=name)  # noqa: E731
+                asec = timed(fn, max(5, a.steps // 2), 2)
+                out["algos"][name] = {"ms_per_step": asec * 1e3, "effective_nnz_per_s": eff / asec}
+            except Exception as e:  # not applicable to this shape
+                out["algos"][name] = {"error": str(e)}
+        cfg["algo"] = algo
 
     # ---- the non-symmetric comparison kernel on the expanded operand ----
     if not a.no_compare:

@@ -126,6 +126,41 @@ SYSTEC_API int systec_mttkrp(int order, int64_t I, int64_t nnz, const int32_t* c
                   systec_stream stream);
 
 /* ------------------------------------------------------------------------
+ * How the updates of the non-leading slots are resolved (all give the same
+ * result up to FP32 summation order):
+ *   SYSTEC_MTTKRP_AUTO     the library chooses from I, R and the dtype
+ *   SYSTEC_MTTKRP_ATOMIC   canonical list; leading slot summed in registers
+ *                          across a run of equal c1 (Sec. 4.2.8), the other
+ *                          run-start slots by device FP32 atomics
+ *   SYSTEC_MTTKRP_LDS      slot views of a prepared tensor with the factor
+ *                          rows staged in LDS by column slices (prepared
+ *                          tensors of small index spaces: a slice of one
+ *                          16-byte vector per row, 8 BF16 or 4 FP32 columns,
+ *                          must fit one workgroup's LDS; with 160 KiB that
+ *                          is I <= 10,220); otherwise EINVAL
+ *   SYSTEC_MTTKRP_VIEWS    slot views of a prepared tensor (systec_mttkrp_t
+ *                          only; EINVAL for the one-shot call)
+ * ---------------------------------------------------------------------- */
+typedef enum {
+  SYSTEC_MTTKRP_AUTO = 0,
+  SYSTEC_MTTKRP_ATOMIC = 1,
+  SYSTEC_MTTKRP_LDS = 2,
+  SYSTEC_MTTKRP_VIEWS = 3
+} systec_mttkrp_algo;
+
+/* The algorithm AUTO runs for this shape: *algo receives ATOMIC for a
+ * one-shot call (prepared == 0), VIEWS for a prepared
+ * tensor. Errors: EINVAL (NULL algo, I or R out of range, bad dtype). */
+SYSTEC_API int systec_mttkrp_choose(int64_t I, systec_dtype bdt, int64_t R, int prepared,
+                                    systec_mttkrp_algo* algo);
+
+/* systec_mttkrp with an explicit algorithm (systec_mttkrp is AUTO; only
+ * AUTO and ATOMIC apply to the one-shot call). */
+SYSTEC_API int systec_mttkrp_ex(int order, int64_t I, int64_t nnz, const int32_t* const* idx,
+                                const float* val, const void* B, systec_dtype bdt, int64_t R,
+                                float* C, systec_mttkrp_algo algo, systec_stream stream);
+
+/* ------------------------------------------------------------------------
  * Comparison kernels without symmetry (the paper's baseline is the same
  * kernel over the full tensor; Sec. 5.2, results normalized to it).
  *
@@ -250,6 +285,12 @@ SYSTEC_API int systec_ssymv_t(const systec_tensor* t, const void* x, systec_dtyp
 /* C = MTTKRP for a prepared tensor; B, C as for systec_mttkrp. */
 SYSTEC_API int systec_mttkrp_t(const systec_tensor* t, const void* B, systec_dtype bdt,
                                int64_t R, float* C, systec_stream stream);
+/* systec_mttkrp_t with an explicit algorithm (systec_mttkrp_t is AUTO: the
+ * slot views).
+ * ATOMIC runs on the tensor's canonical list (its first view). */
+SYSTEC_API int systec_mttkrp_t_ex(const systec_tensor* t, const void* B, systec_dtype bdt,
+                                  int64_t R, float* C, systec_mttkrp_algo algo,
+                                  systec_stream stream);
 
 /* ------------------------------------------------------------------------
  * Serving: many prepared operands resident in HBM, requests of mixed kind

@@ -113,10 +113,29 @@ def _idx_ptrs(idx, name="idx"):
     return ptr_array([t.data_ptr() for t in idx])
 
 
-def mttkrp(idx, val, B, out=None, stream=None):
+MTTKRP_ALGOS = {"auto": 0, "atomic": 1, "lds": 2, "views": 3}
+
+
+def _algo(name):
+    if name not in MTTKRP_ALGOS:
+        raise ValueError(f"algo must be one of {sorted(MTTKRP_ALGOS)}")
+    return MTTKRP_ALGOS[name]
+
+
+def mttkrp_choose(I, R, bf16, prepared):
+    """Name of the algorithm "auto" runs for this shape ("atomic" for the
+    one-shot call, "views" or "lds" for a prepared tensor)."""
+    code = ctypes.c_int32(0)
+    call("systec_mttkrp_choose", I, 1 if bf16 else 0, R, 1 if prepared else 0,
+         ctypes.byref(code))
+    return {v: k for k, v in MTTKRP_ALGOS.items()}[code.value]
+
+
+def mttkrp(idx, val, B, out=None, stream=None, algo="auto"):
     """Symmetric MTTKRP: idx is a list of `order` (3..5) int32 index tensors of
     canonical COO (each tuple ascending, list sorted), val float32, B (I x R)
-    float32 or bfloat16. Returns C (I x R) float32."""
+    float32 or bfloat16. Returns C (I x R) float32. algo: "auto" or "atomic"
+    (the other algorithms need a prepared tensor, see Tensor.mttkrp)."""
     torch = _torch()
     order = len(idx)
     I, R = B.shape
@@ -128,8 +147,8 @@ def mttkrp(idx, val, B, out=None, stream=None):
     if tuple(C.shape) != (I, R):
         raise ValueError("out must be I x R")
     pp, keep = _idx_ptrs(idx)
-    call("systec_mttkrp", order, I, val.numel(), pp, _p(val), _p(B), _dtype_code(B), R, _p(C),
-         _stream(stream))
+    call("systec_mttkrp_ex", order, I, val.numel(), pp, _p(val), _p(B), _dtype_code(B), R, _p(C),
+         _algo(algo), _stream(stream))
     del keep
     return C
 
@@ -287,7 +306,10 @@ class Tensor:
         call("systec_ssymv_t", self._h, _p(x), _dtype_code(x), _p(y), _stream(stream))
         return y
 
-    def mttkrp(self, B, out=None, stream=None):
+    def mttkrp(self, B, out=None, stream=None, algo="auto"):
+        """C = MTTKRP of the prepared tensor; algo: "auto", "views" (slot
+        views), "lds" (slot views with B staged in LDS; small index spaces)
+        or "atomic" (the canonical list with device atomics)."""
         torch = _torch()
         _dev(B, None, "B")
         I, R = B.shape
@@ -297,7 +319,8 @@ class Tensor:
         _dev(C, torch.float32, "out")
         if tuple(C.shape) != (I, R):
             raise ValueError("out must be I x R")
-        call("systec_mttkrp_t", self._h, _p(B), _dtype_code(B), R, _p(C), _stream(stream))
+        call("systec_mttkrp_t_ex", self._h, _p(B), _dtype_code(B), R, _p(C), _algo(algo),
+             _stream(stream))
         return C
 
     def close(self):

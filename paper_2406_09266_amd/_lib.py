@@ -32,6 +32,8 @@ SIGNATURES = {
     "systec_ssymv": [I64, I64, P, P, P, P, I32, P, P],
     "systec_syprd": [I64, I64, P, P, P, P, I32, P, P],
     "systec_mttkrp": [I32, I64, I64, PP, P, P, I32, I64, P, P],
+    "systec_mttkrp_choose": [I64, I32, I64, I32, P],
+    "systec_mttkrp_ex": [I32, I64, I64, PP, P, P, I32, I64, P, I32, P],
     "systec_spmv_csr": [I64, I64, P, P, P, P, I32, P, P],
     "systec_mttkrp_full": [I32, I64, I64, PP, P, P, I32, I64, P, P],
     "systec_expand_csr_size": [I64, I64, P, P, PI64, P],
@@ -50,6 +52,7 @@ SIGNATURES = {
     "systec_tensor_destroy": [P],
     "systec_ssymv_t": [P, P, I32, P, P],
     "systec_mttkrp_t": [P, P, I32, I64, P, P],
+    "systec_mttkrp_t_ex": [P, P, I32, I64, P, I32, P],
     "systec_kernel_timing": [I32],
     "systec_kernel_timing_read": [PD, PI64],
 }

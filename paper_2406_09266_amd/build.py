@@ -21,7 +21,7 @@ INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(PKG, "libsystec.so")
 BUILD_DIR = os.path.join(ROOT, "_build", "systec")
 
-SOURCES = ["abi.cpp", "ssymv.hip", "mttkrp.hip", "aux.hip", "plan.hip", "serve.cpp",
+SOURCES = ["abi.cpp", "ssymv.hip", "mttkrp.hip", "mttkrp_lds.hip", "aux.hip", "plan.hip", "serve.cpp",
            "serve_kernel.hip"]
 
 ARCH = "gfx950"

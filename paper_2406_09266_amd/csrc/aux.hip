@@ -86,23 +86,58 @@ enum : unsigned int {
   kListOrder = 64u,
 };
 
-__global__ void validate_csr_kernel(int n, int nnz, const int32_t* __restrict__ rowptr,
-                                    const int32_t* __restrict__ col, unsigned int* flags) {
+// Row of entry q: the last r in [0, n) with rowptr[r] <= q. Reads rowptr
+// only within [0, n], so it stays in bounds whatever rowptr holds.
+__device__ __forceinline__ int row_of(const int32_t* __restrict__ rowptr, int n, int q) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (rowptr[mid] <= q) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Moves r forward to the row of entry q (a few steps, else a search).
+__device__ __forceinline__ int advance_row(const int32_t* __restrict__ rowptr, int n, int r, int q) {
+  for (int k = 0; k < 4; ++k) {
+    if (r + 1 >= n || rowptr[r + 1] > q) return r;
+    ++r;
+  }
+  return (r + 1 >= n || rowptr[r + 1] > q) ? r : row_of(rowptr, n, q);
+}
+
+// Entries are checked in chunks of kChunk consecutive entries per thread, so
+// a long row is spread over many threads (rows of 10^5 entries occur in
+// graph matrices).
+constexpr int kChunk = 16;
+
+__global__ void validate_rowptr_kernel(int n, int nnz, const int32_t* __restrict__ rowptr,
+                                       unsigned int* flags) {
   const int stride = gridDim.x * blockDim.x;
   for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
     const int a = rowptr[r], b = rowptr[r + 1];
-    if (r == 0 && a != 0) atomicOr(flags, kBadRowptr);
-    if (r == n - 1 && b != nnz) atomicOr(flags, kBadRowptr);
-    if (a > b || a < 0 || b > nnz) {
+    if ((r == 0 && a != 0) || (r == n - 1 && b != nnz) || a > b || a < 0 || b > nnz)
       atomicOr(flags, kBadRowptr);
-      continue;
-    }
+  }
+}
+
+__global__ void validate_csr_entries_kernel(int n, int nnz, const int32_t* __restrict__ rowptr,
+                                            const int32_t* __restrict__ col, unsigned int* flags) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  const int64_t chunks = (static_cast<int64_t>(nnz) + kChunk - 1) / kChunk;
+  for (int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; k < chunks;
+       k += stride) {
+    const int q0 = static_cast<int>(k * kChunk);
+    const int q1 = min(nnz, q0 + kChunk);
+    int r = row_of(rowptr, n, q0);
     unsigned int f = 0;
-    for (int q = a; q < b; ++q) {
+    for (int q = q0; q < q1; ++q) {
+      r = advance_row(rowptr, n, r, q);
       const int c = col[q];
       if (c < 0 || c >= n) f |= kColRange;
       if (c < r) f |= kBelowDiag;
-      if (q > a && col[q - 1] >= c) f |= kRowOrder;
+      if (q > 0 && q > rowptr[r] && col[q - 1] >= c) f |= kRowOrder;
     }
     if (f) atomicOr(flags, f);
   }
@@ -146,13 +181,22 @@ std::string describe_flags(unsigned int f) {
 }
 
 // ---- expansion to the full operand ------------------------------------------
-__global__ void csr_count_diag_kernel(int n, const int32_t* __restrict__ rowptr,
+__global__ void csr_count_diag_kernel(int n, int nnz, const int32_t* __restrict__ rowptr,
                                       const int32_t* __restrict__ col,
                                       unsigned long long* __restrict__ diag) {
-  const int stride = gridDim.x * blockDim.x;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  const int64_t chunks = (static_cast<int64_t>(nnz) + kChunk - 1) / kChunk;
   unsigned long long d = 0;
-  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride)
-    for (int q = rowptr[r]; q < rowptr[r + 1]; ++q) d += (col[q] == r);
+  for (int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; k < chunks;
+       k += stride) {
+    const int q0 = static_cast<int>(k * kChunk);
+    const int q1 = min(nnz, q0 + kChunk);
+    int r = row_of(rowptr, n, q0);
+    for (int q = q0; q < q1; ++q) {
+      r = advance_row(rowptr, n, r, q);
+      d += (col[q] == r);
+    }
+  }
   if (d) atomicAdd(diag, d);
 }
 
@@ -317,7 +361,11 @@ int launch_expansion_stats(int order, int64_t nnz, const int32_t* const* idx,
 
 int launch_validate_csr_upper(int64_t n, int64_t nnz, const int32_t* rowptr,
                               const int32_t* col, unsigned int* d_flags, hipStream_t s) {
-  validate_csr_kernel<<<dim3(grid_for(n, 256)), dim3(256), 0, s>>>(
+  validate_rowptr_kernel<<<dim3(grid_for(n, 256)), dim3(256), 0, s>>>(
+      static_cast<int>(n), static_cast<int>(nnz), rowptr, d_flags);
+  int rc = check_launch("validate rowptr kernel");
+  if (rc || nnz == 0) return rc;
+  validate_csr_entries_kernel<<<dim3(grid_for((nnz + kChunk - 1) / kChunk, 256)), dim3(256), 0, s>>>(
       static_cast<int>(n), static_cast<int>(nnz), rowptr, col, d_flags);
   return check_launch("validate csr kernel");
 }
@@ -342,8 +390,9 @@ int expand_csr_size(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t
   if (rc) return rc;
   if ((rc = check_hip(hipMemsetAsync(d.p, 0, sizeof(unsigned long long), s), "hipMemsetAsync")))
     return rc;
-  csr_count_diag_kernel<<<dim3(grid_for(n, 256)), dim3(256), 0, s>>>(
-      static_cast<int>(n), rowptr, col, static_cast<unsigned long long*>(d.p));
+  csr_count_diag_kernel<<<dim3(grid_for((nnz + kChunk - 1) / kChunk, 256)), dim3(256), 0, s>>>(
+      static_cast<int>(n), static_cast<int>(nnz), rowptr, col,
+      static_cast<unsigned long long*>(d.p));
   if ((rc = check_launch("count diagonal kernel"))) return rc;
   unsigned long long diag = 0;
   if ((rc = check_hip(hipMemcpyAsync(&diag, d.p, sizeof(diag), hipMemcpyDeviceToHost, s),

@@ -61,6 +61,9 @@ int launch_syprd(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* c
 int launch_mttkrp(int order, int64_t I, int64_t nnz, const int32_t* const* idx,
                   const float* val, const void* B, systec_dtype bdt, int64_t R, float* C,
                   bool symmetric, hipStream_t s);
+// MTTKRP over the slot views with B staged in LDS by column slices; usable
+// when mttkrp_lds_width(I, bdt, R) > 0 (the slice width in columns).
+int mttkrp_lds_width(int64_t I, systec_dtype bdt, int64_t R);
 int launch_quantize_bf16(const float* in, uint16_t* out, int64_t n, hipStream_t s);
 int launch_expansion_stats(int order, int64_t nnz, const int32_t* const* idx,
                            unsigned long long* d_counts /* 17 */, hipStream_t s);
@@ -88,6 +91,8 @@ int expand_coo(int order, int64_t I, int64_t nnz, const int32_t* const* idx, con
 // starts a run of equal indices, sorted by their slot-t index (stable), so
 // that every output update of view t is a segmented reduction.
 constexpr int kPanelTile = 512;
+struct ServeTensor;
+struct ServeUnit;
 struct Tensor {
   int kind = 0;  // 0: matrix (panel format), 1: tensor (slot views)
   int order = 0;
@@ -111,6 +116,9 @@ struct Tensor {
   int64_t vnnz[5] = {0, 0, 0, 0, 0};
   int32_t* vidx[5][5] = {};
   float* vval[5] = {};
+  // serving (built at registration)
+  ServeTensor* d_serve = nullptr;
+  ServeUnit* d_units = nullptr;
   std::vector<void*> allocations;
 };
 int tensor_create_csr(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col,
@@ -122,41 +130,72 @@ int launch_ssymv_panel(const Tensor* t, const void* x, systec_dtype xdt, float* 
                        hipStream_t s);
 int launch_mttkrp_views(const Tensor* t, const void* B, systec_dtype bdt, int64_t R, float* C,
                         hipStream_t s);
+int launch_mttkrp_views_lds(const Tensor* t, const void* B, systec_dtype bdt, int64_t R, float* C,
+                            hipStream_t s);
 
 // ---- serving step (serve_kernel.hip) ----------------------------------------
-// One work item of a serving step: a chunk of a prepared matrix (SSYMV) or a
-// range of one slot view of a prepared tensor (MTTKRP), with the request's
-// input and output.
-struct ServeItem {
-  int32_t kind;   // 0: SSYMV panel chunk, 1: MTTKRP slot-view range
-  int32_t dtype;  // systec_dtype of the input
-  int32_t order;
-  int32_t slot;   // view (MTTKRP)
-  int32_t dim;    // n or I
-  int32_t H;      // panel rows (SSYMV)
-  int32_t R;      // columns (MTTKRP), <= 64
-  int32_t panel;  // (SSYMV)
-  int32_t begin;  // tile range (SSYMV) or entry range (MTTKRP)
-  int32_t end;
-  int32_t pad0, pad1;
-  const void* p[5];  // SSYMV: pcol, prow, pval; MTTKRP: the view's index arrays
-  const float* val;  // MTTKRP: the view's values
-  const void* in;    // x or B
-  float* out;        // y or C
+// A prepared operand as the serving kernels see it (device memory, built when
+// the operand is registered), with its work units: SSYMV {panel, first tile,
+// end tile}, MTTKRP {view, first entry, end entry}.
+struct ServeUnit {
+  int32_t a, b, c, d;
 };
-struct ZeroSeg {
-  float* ptr;
-  int64_t count;
+struct ServeTensor {
+  int32_t kind;   // 0: matrix (panel format), 1: tensor (slot views)
+  int32_t order;
+  int32_t dim;    // n or I
+  int32_t H;      // panel rows (matrix)
+  const void* p[5][5];  // matrix: p[0] = {pcol, prow, pval}; tensor: p[v] = view v's indices
+  const float* val[5];  // tensor: view values
+  const ServeUnit* units;
+};
+// One request's share of a step: units [unit0, unit0 + count) of its
+// operand run as items [item0, item0 + count) of the launch.
+struct StepReq {
+  const ServeTensor* t;
+  const void* in;  // x or B
+  float* out;      // y or C
+  int32_t unit0, item0, R, dtype;
+};
+// Everything a step launch needs travels in its kernel arguments (1.3 KB),
+// so a step costs no host-to-device copy.
+constexpr int kStepReqs = 32;
+struct StepArgs {
+  int32_t nreq, nitems;
+  StepReq req[kStepReqs];  // ascending item0
+};
+struct ZeroArgs {
+  int32_t n, pad;
+  float* ptr[kStepReqs];
+  int64_t count[kStepReqs];
 };
 constexpr int kServeBlock = 512;       // SSYMV step kernel
 constexpr int kServeMttkrpBlock = 256; // MTTKRP step kernel
 constexpr int kServeLds = 16384 * 4;   // bytes: the row sums of one panel
-// Zeroes the segments and resets the step's four work counters.
-int launch_serve_zero(const ZeroSeg* d_zero, int nzero, int* d_counters, hipStream_t s);
-// Runs a persistent step kernel over items of one kind (0: SSYMV; 3, 4, 5:
-// MTTKRP of that order).
-int launch_serve_items(int kind, const ServeItem* d_items, int nitems, int* d_counter, int grid,
-                       hipStream_t s);
+// Work queues of the step launches on one stream: queue k's counter is
+// next[k * kQueueStride] (separate cache lines).
+constexpr int kStepQueues = 8;
+constexpr int kQueueStride = 64;
+struct StepCounter {
+  int next[kStepQueues * kQueueStride];
+};
+// Resets the queues of `nsets` counter sets and zeroes the outputs of newly
+// admitted requests; runs on a stream before its step launches.
+int launch_serve_prologue(const ZeroArgs& z, StepCounter* ctr, int nsets, hipStream_t s);
+// Step kernel variants: kind 0 is SSYMV (one variant); kinds 3, 4, 5 are
+// MTTKRP of that order, variant = 4 * (input is BF16) + lane class (R <= 8,
+// 16, 32, 64).
+constexpr int kStepVariants = 8;
+inline int step_variant(int dtype, int64_t R) {
+  const int lane_class = R <= 8 ? 0 : R <= 16 ? 1 : R <= 32 ? 2 : 3;
+  return (dtype == SYSTEC_BF16 ? 4 : 0) + lane_class;
+}
+// Runs a persistent step kernel over the items of one (kind, variant) with
+// at most `grid` workgroups, taking items from the counter set `ctr`.
+int launch_serve_step(int kind, int variant, const StepArgs& a, int grid, StepCounter* ctr,
+                      hipStream_t s);
+// Workgroups of a step kernel that fit on one CU at once.
+int serve_blocks_per_cu(int kind, int variant, int* blocks);
 
 // ---- multiplicity rule (host and device) ----------------------------------
 // For a sorted tuple of `order` indices whose equality pattern is `mask`

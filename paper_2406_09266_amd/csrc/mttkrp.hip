@@ -48,18 +48,43 @@ __global__ __launch_bounds__(kBlock) void mttkrp_tiles_kernel(int nnz, IdxPtrs i
                                         ncols);
 }
 
-// One wave per tile of kTileE consecutive entries of slot view t.
-template <int N, typename BT, int L>
-__global__ __launch_bounds__(kBlock) void mttkrp_view_kernel(int t, int nnz, IdxPtrs idx,
-                                                           const float* __restrict__ val,
-                                                           const BT* __restrict__ B, int ldb,
-                                                           float* __restrict__ C, int ldc,
-                                                           int col0, int ncols) {
-  const int64_t wave = static_cast<int64_t>(blockIdx.x) * kWaves + threadIdx.x / kWave;
+// The N slot views of a prepared tensor, processed by one launch: blocks
+// [block0[t], block0[t+1]) take view t, one wave per tile of kTileE entries.
+struct ViewSet {
+  IdxPtrs idx[5];
+  const float* val[5];
+  int nnz[5];
+  int block0[6];
+};
+
+template <int N, typename BT, int L, int T>
+__device__ __forceinline__ void view_block(const ViewSet& vs, int b, const BT* __restrict__ B,
+                                           int ldb, float* __restrict__ C, int ldc, int col0,
+                                           int ncols) {
+  const int64_t wave = static_cast<int64_t>(b - vs.block0[T]) * kWaves + threadIdx.x / kWave;
   const int64_t e0 = wave * kTileE;
-  if (e0 >= nnz) return;
-  const int e1 = static_cast<int>(min<int64_t>(nnz, e0 + kTileE));
-  mttkrp_view_tile<N, BT, L>(t, static_cast<int>(e0), e1, idx, val, B, ldb, C, ldc, col0, ncols);
+  if (e0 >= vs.nnz[T]) return;
+  const int e1 = static_cast<int>(min<int64_t>(vs.nnz[T], e0 + kTileE));
+  mttkrp_view_tile<N, BT, L, T>(static_cast<int>(e0), e1, vs.idx[T], vs.val[T], B, ldb, C, ldc,
+                                col0, ncols);
+}
+
+template <int N, typename BT, int L>
+__global__ __launch_bounds__(kBlock) void mttkrp_views_kernel(ViewSet vs,
+                                                            const BT* __restrict__ B, int ldb,
+                                                            float* __restrict__ C, int ldc,
+                                                            int col0, int ncols) {
+  const int b = blockIdx.x;
+  if (b < vs.block0[1]) {
+    view_block<N, BT, L, 0>(vs, b, B, ldb, C, ldc, col0, ncols);
+  } else if (b < vs.block0[2]) {
+    view_block<N, BT, L, 1>(vs, b, B, ldb, C, ldc, col0, ncols);
+  } else if (N == 3 || b < vs.block0[3]) {
+    view_block<N, BT, L, 2>(vs, b, B, ldb, C, ldc, col0, ncols);
+  } else if constexpr (N > 3) {
+    if (N == 4 || b < vs.block0[4]) view_block<N, BT, L, 3>(vs, b, B, ldb, C, ldc, col0, ncols);
+    else if constexpr (N > 4) view_block<N, BT, L, 4>(vs, b, B, ldb, C, ldc, col0, ncols);
+  }
 }
 
 template <int N, typename BT, int L, bool kSym>
@@ -129,30 +154,32 @@ int launch_mttkrp(int order, int64_t I, int64_t nnz, const int32_t* const* idx,
 namespace {
 
 template <int N, typename BT, int L>
-void launch_view_one(int t, int nnz, const IdxPtrs& ip, const float* val, const BT* B, int ldb,
-                     float* C, int ldc, int col0, int ncols, hipStream_t s) {
-  const int64_t tiles = (static_cast<int64_t>(nnz) + kTileE - 1) / kTileE;
-  const int64_t blocks = (tiles + kWaves - 1) / kWaves;
-  if (blocks == 0) return;
-  mttkrp_view_kernel<N, BT, L>
-      <<<dim3(blocks), dim3(kBlock), 0, s>>>(t, nnz, ip, val, B, ldb, C, ldc, col0, ncols);
+void launch_views_cols(const ViewSet& vs, const BT* B, int ldb, float* C, int ldc, int col0,
+                       int ncols, hipStream_t s) {
+  mttkrp_views_kernel<N, BT, L>
+      <<<dim3(vs.block0[N]), dim3(kBlock), 0, s>>>(vs, B, ldb, C, ldc, col0, ncols);
 }
 
 template <int N, typename BT>
 void launch_views_typed(const Tensor* tn, const BT* B, int R, float* C, hipStream_t s) {
+  ViewSet vs{};
+  int64_t blocks = 0;
   for (int t = 0; t < N; ++t) {
-    const int m = static_cast<int>(tn->vnnz[t]);
-    if (m == 0) continue;
-    IdxPtrs ip{};
-    for (int q = 0; q < N; ++q) ip.p[q] = tn->vidx[t][q];
-    const float* val = tn->vval[t];
-    if (R <= 8) launch_view_one<N, BT, 8>(t, m, ip, val, B, R, C, R, 0, R, s);
-    else if (R <= 16) launch_view_one<N, BT, 16>(t, m, ip, val, B, R, C, R, 0, R, s);
-    else if (R <= 32) launch_view_one<N, BT, 32>(t, m, ip, val, B, R, C, R, 0, R, s);
-    else
-      for (int c0 = 0; c0 < R; c0 += 64)
-        launch_view_one<N, BT, 64>(t, m, ip, val, B, R, C, R, c0, std::min(64, R - c0), s);
+    for (int q = 0; q < N; ++q) vs.idx[t].p[q] = tn->vidx[t][q];
+    vs.val[t] = tn->vval[t];
+    vs.nnz[t] = static_cast<int>(tn->vnnz[t]);
+    vs.block0[t] = static_cast<int>(blocks);
+    const int64_t tiles = (tn->vnnz[t] + kTileE - 1) / kTileE;
+    blocks += (tiles + kWaves - 1) / kWaves;
   }
+  for (int t = N; t <= 5; ++t) vs.block0[t] = static_cast<int>(blocks);
+  if (blocks == 0) return;
+  if (R <= 8) launch_views_cols<N, BT, 8>(vs, B, R, C, R, 0, R, s);
+  else if (R <= 16) launch_views_cols<N, BT, 16>(vs, B, R, C, R, 0, R, s);
+  else if (R <= 32) launch_views_cols<N, BT, 32>(vs, B, R, C, R, 0, R, s);
+  else
+    for (int c0 = 0; c0 < R; c0 += 64)
+      launch_views_cols<N, BT, 64>(vs, B, R, C, R, c0, std::min(64, R - c0), s);
 }
 
 template <int N>

@@ -130,11 +130,13 @@ __device__ __forceinline__ void mttkrp_canonical_tile(int e0, int e1, const IdxP
   if (cur >= 0 && lc.col_ok) atomic_add_noret(C + static_cast<int64_t>(cur) * ldc + lc.col, acc);
 }
 
-// One tile of slot view t (see plan.hip): every entry updates C[c_t] with its
-// slot-t coefficient; the view is sorted by c_t, so the updates are register
-// sums written once per run of equal c_t.
-template <int N, typename BT, int L>
-__device__ __forceinline__ void mttkrp_view_tile(int t, int e0, int e1, const IdxPtrs& idx,
+// One tile of slot view T (see plan.hip): every entry updates C[c_T] with its
+// slot-T coefficient; the view is sorted by c_T, so the updates are register
+// sums written once per run of equal c_T. T is a template parameter so that
+// only the N-1 factor rows of the product are gathered and the loop stays
+// straight-line code (callers switch on the slot once per tile).
+template <int N, typename BT, int L, int T>
+__device__ __forceinline__ void mttkrp_view_tile(int e0, int e1, const IdxPtrs& idx,
                                                  const float* __restrict__ val,
                                                  const BT* __restrict__ B, int ldb,
                                                  float* __restrict__ C, int ldc, int col0,
@@ -155,42 +157,51 @@ __device__ __forceinline__ void mttkrp_view_tile(int t, int e0, int e1, const Id
       for (int s = 0; s < N; ++s) c[u][s] = ok[u] ? idx.p[s][e] : 0;
       v[u] = ok[u] ? val[e] : 0.0f;
     }
-    // All N factor rows are gathered unconditionally (the slot-t row is the
-    // output row: sorted, so it is nearly always cached); a runtime test on
-    // the slot would split the gathers into dependent branches.
     float b[kUnroll][N];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u)
 #pragma unroll
-      for (int s = 0; s < N; ++s) b[u][s] = load_f32(B, static_cast<int64_t>(c[u][s]) * ldb + lc.col);
-    float prod[kUnroll];
-    int out[kUnroll];
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      float p = 1.0f;
-      int o = c[u][0];
-#pragma unroll
-      for (int s = 0; s < N; ++s) {
-        o = (s == t) ? c[u][s] : o;
-        p *= (s == t) ? 1.0f : b[u][s];
-      }
-      prod[u] = p;
-      out[u] = o;
-    }
+      for (int s = 0; s < N; ++s)
+        b[u][s] = (s == T) ? 1.0f : load_f32(B, static_cast<int64_t>(c[u][s]) * ldb + lc.col);
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       if (!ok[u]) continue;
-      const float k = coef_table<N>().coef[equality_mask_of(c[u], N)][t];
-      if (out[u] != cur) {
+      float p = 1.0f;
+#pragma unroll
+      for (int s = 0; s < N; ++s)
+        if (s != T) p *= b[u][s];
+      const float k = coef_table<N>().coef[equality_mask_of(c[u], N)][T];
+      const int out = c[u][T];
+      if (out != cur) {
         if (cur >= 0 && lc.col_ok)
           atomic_add_noret(C + static_cast<int64_t>(cur) * ldc + lc.col, acc);
-        cur = out[u];
+        cur = out;
         acc = 0.0f;
       }
-      acc += k * v[u] * prod[u];
+      acc += k * v[u] * p;
     }
   }
   if (cur >= 0 && lc.col_ok) atomic_add_noret(C + static_cast<int64_t>(cur) * ldc + lc.col, acc);
+}
+
+// Runs the view tile of slot t (a value uniform across the wave).
+template <int N, typename BT, int L>
+__device__ __forceinline__ void mttkrp_view_tile_slot(int t, int e0, int e1, const IdxPtrs& idx,
+                                                      const float* __restrict__ val,
+                                                      const BT* __restrict__ B, int ldb,
+                                                      float* __restrict__ C, int ldc, int col0,
+                                                      int ncols) {
+  switch (t) {
+    case 0: mttkrp_view_tile<N, BT, L, 0>(e0, e1, idx, val, B, ldb, C, ldc, col0, ncols); break;
+    case 1: mttkrp_view_tile<N, BT, L, 1>(e0, e1, idx, val, B, ldb, C, ldc, col0, ncols); break;
+    case 2: mttkrp_view_tile<N, BT, L, 2>(e0, e1, idx, val, B, ldb, C, ldc, col0, ncols); break;
+    case 3:
+      if constexpr (N > 3) mttkrp_view_tile<N, BT, L, 3>(e0, e1, idx, val, B, ldb, C, ldc, col0, ncols);
+      break;
+    default:
+      if constexpr (N > 4) mttkrp_view_tile<N, BT, L, 4>(e0, e1, idx, val, B, ldb, C, ldc, col0, ncols);
+      break;
+  }
 }
 
 }  // namespace dev

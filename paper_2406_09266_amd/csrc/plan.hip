@@ -63,23 +63,20 @@ __global__ void panel_keys_kernel(int nnz, int hbits, const int32_t* __restrict_
   }
 }
 
-// Entries per panel from the sorted keys: panel p starts at the first key
-// whose panel field is >= p (binary search; no atomics on hot counters).
-__global__ void panel_count_kernel(int nnz, int hbits, int npanels,
-                                   const unsigned long long* __restrict__ keys,
-                                   int32_t* __restrict__ counts) {
+// First sorted key of every panel: entry e starts panels (panel(e-1),
+// panel(e)] (empty panels start where the next non-empty one does), and the
+// last entry closes the remaining panels with nnz.
+__global__ void panel_starts_kernel(int nnz, int hbits, int npanels,
+                                    const unsigned long long* __restrict__ keys,
+                                    int32_t* __restrict__ start) {
   const int stride = gridDim.x * blockDim.x;
-  auto first_of = [&](long long p) {
-    int lo = 0, hi = nnz;  // first s with panel(keys[s]) >= p
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (static_cast<long long>(keys[mid] >> (31 + hbits)) < p) lo = mid + 1;
-      else hi = mid;
-    }
-    return lo;
-  };
-  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < npanels; p += stride)
-    counts[p] = first_of(p + 1) - first_of(p);
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += stride) {
+    const int pe = static_cast<int>(keys[e] >> (31 + hbits));
+    const int pp = e == 0 ? -1 : static_cast<int>(keys[e - 1] >> (31 + hbits));
+    for (int p = pp + 1; p <= pe && p < npanels; ++p) start[p] = e;
+    if (e == nnz - 1)
+      for (int p = pe + 1; p <= npanels; ++p) start[p] = nnz;
+  }
 }
 
 __global__ void panel_scatter_kernel(int nnz, int hbits, const unsigned long long* __restrict__ keys,
@@ -254,13 +251,18 @@ int tensor_create_csr(int64_t n, int64_t nnz, const int32_t* rowptr, const int32
     rc = check_launch("panel key kernels");
     if (!rc) rc = radix_sort_pairs(kin, kout, vin, vout, nz, 31 + hbits + bits_for(P + 1), s);
     if (!rc) {
-      panel_count_kernel<<<grid_for(P, 256), 256, 0, s>>>(nz, hbits, P, kout, counts);
-      rc = check_launch("panel count kernel");
+      panel_starts_kernel<<<grid_for(nz, 256), 256, 0, s>>>(nz, hbits, P, kout, d_start);
+      rc = check_launch("panel start kernel");
     }
+    std::vector<int32_t> h_first(P + 1, 0);
     if (!rc)
-      rc = check_hip(hipMemcpyAsync(h_counts.data(), counts, P * sizeof(int32_t),
+      rc = check_hip(hipMemcpyAsync(h_first.data(), d_start, (P + 1) * sizeof(int32_t),
                                     hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
     if (!rc) rc = check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+    for (int p = 0; p < P && !rc; ++p) h_counts[p] = h_first[p + 1] - h_first[p];
+    if (!rc)
+      rc = check_hip(hipMemcpyAsync(counts, h_counts.data(), P * sizeof(int32_t),
+                                    hipMemcpyHostToDevice, s), "hipMemcpyAsync");
     if (rc) {
       tensor_free(t);
       return rc;

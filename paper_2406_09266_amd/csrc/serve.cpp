@@ -10,6 +10,7 @@
 // run.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -21,205 +22,9 @@
 namespace systec {
 namespace {
 
-constexpr int kRing = 4;                   // step buffers (> steps in flight)
-constexpr int kMaxItems = 1 << 16;         // work items per step
-constexpr int kMaxZero = 1 << 16;          // output pieces to zero per step
-constexpr int64_t kZeroPiece = 16384;      // floats per zeroed piece
-constexpr int64_t kViewUnit = 64 * 256;    // entries per MTTKRP work unit
+constexpr int kRing = 4;                   // step events (> steps in flight)
+constexpr int64_t kViewUnit = 16 * 256;    // entries per MTTKRP work unit (4 tiles per wave)
 constexpr int kSsymvUnitTiles = 64;        // panel tiles per SSYMV work unit
-
-class GpuExecutor {
- public:
-  int init(int device, std::string* err) {
-    device_ = device;
-    hipError_t e = hipSetDevice(device);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking);
-    for (int k = 0; k < 3 && e == hipSuccess; ++k)
-      e = hipStreamCreateWithFlags(&mstream_[k], hipStreamNonBlocking);
-    int cus = 0;
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
-    grid_ = std::max(1, cus) * 2;   // SSYMV: two 512-thread workgroups (64 KiB LDS each) per CU
-    grid2_ = std::max(1, cus) * 8;  // MTTKRP: eight 256-thread workgroups per CU
-    for (int i = 0; i < kRing && e == hipSuccess; ++i) {
-      e = hipHostMalloc(reinterpret_cast<void**>(&h_items_[i]), kMaxItems * sizeof(ServeItem));
-      if (e == hipSuccess)
-        e = hipHostMalloc(reinterpret_cast<void**>(&h_zero_[i]), kMaxZero * sizeof(ZeroSeg));
-      if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&d_items_[i]), kMaxItems * sizeof(ServeItem));
-      if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&d_zero_[i]), kMaxZero * sizeof(ZeroSeg));
-      if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&d_counter_[i]), 4 * sizeof(int));
-      if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_[i], hipEventDisableTiming);
-      for (int k = 0; k < 3 && e == hipSuccess; ++k)
-        e = hipEventCreateWithFlags(&mev_[i][k], hipEventDisableTiming);
-      if (e == hipSuccess) e = hipEventCreateWithFlags(&evz_[i], hipEventDisableTiming);
-    }
-    if (e != hipSuccess) {
-      *err = std::string("serving executor init: ") + hipGetErrorString(e);
-      return serve::kEdevice;
-    }
-    return serve::kOk;
-  }
-
-  ~GpuExecutor() {
-    if (stream_) (void)hipStreamSynchronize(stream_);
-    for (hipStream_t ms : mstream_)
-      if (ms) (void)hipStreamSynchronize(ms);
-    for (int i = 0; i < kRing; ++i) {
-      if (h_items_[i]) (void)hipHostFree(h_items_[i]);
-      if (h_zero_[i]) (void)hipHostFree(h_zero_[i]);
-      if (d_items_[i]) (void)hipFree(d_items_[i]);
-      if (d_zero_[i]) (void)hipFree(d_zero_[i]);
-      if (d_counter_[i]) (void)hipFree(d_counter_[i]);
-      if (ev_[i]) (void)hipEventDestroy(ev_[i]);
-      for (hipEvent_t me : mev_[i])
-        if (me) (void)hipEventDestroy(me);
-      if (evz_[i]) (void)hipEventDestroy(evz_[i]);
-    }
-    if (stream_) (void)hipStreamDestroy(stream_);
-    for (hipStream_t ms : mstream_)
-      if (ms) (void)hipStreamDestroy(ms);
-  }
-
-  uint64_t request_bytes(const serve::TensorEntry& t, int dtype, int64_t R) const {
-    const uint64_t es = dtype == SYSTEC_BF16 ? 2 : 4;
-    const uint64_t cols = t.kind == 0 ? 1 : static_cast<uint64_t>(R);
-    return static_cast<uint64_t>(t.dim) * cols * (es + 4);  // input + FP32 output
-  }
-
-  int launch(const serve::Plan& plan, std::string* err) {
-    size_t pieces = 0;
-    for (const serve::Request* r : plan.zero)
-      pieces += (r->tensor->dim * (r->tensor->kind == 0 ? 1 : r->R) + kZeroPiece - 1) / kZeroPiece;
-    if (plan.items.size() > static_cast<size_t>(kMaxItems) || pieces > static_cast<size_t>(kMaxZero)) {
-      *err = "serving step too large for the executor's buffers";
-      return serve::kEinval;
-    }
-    (void)hipSetDevice(device_);
-    const int slot = static_cast<int>(plan.step_id % kRing);
-    // the slot's previous step has completed (fewer than kRing steps in flight)
-    // items grouped by kernel: SSYMV, then MTTKRP of order 3, 4, 5
-    std::vector<ServeItem> groups[4];
-    for (size_t k = 0; k < plan.items.size(); ++k) {
-      const serve::PlanItem& pi = plan.items[k];
-      const Tensor* t = static_cast<const Tensor*>(pi.tensor->payload);
-      const serve::Unit& u = *pi.unit;
-      ServeItem it{};
-      it.dtype = pi.req->dtype;
-      it.order = t->order;
-      it.dim = static_cast<int32_t>(t->dim);
-      it.in = pi.req->in;
-      it.out = pi.req->out;
-      if (t->kind == 0) {
-        it.kind = 0;
-        it.H = t->panel_rows;
-        it.panel = u.a;
-        it.begin = u.b;
-        it.end = u.c;
-        it.p[0] = t->pcol;
-        it.p[1] = t->prow;
-        it.p[2] = t->pval;
-        groups[0].push_back(it);
-      } else {
-        it.kind = 1;
-        it.R = static_cast<int32_t>(pi.req->R);
-        it.slot = u.a;
-        it.begin = u.b;
-        it.end = u.c;
-        for (int q = 0; q < t->order; ++q) it.p[q] = t->vidx[u.a][q];
-        it.val = t->vval[u.a];
-        groups[t->order - 2].push_back(it);
-      }
-    }
-    ServeItem* hi = h_items_[slot];
-    int offs[4], cnt[4], total = 0;
-    for (int g = 0; g < 4; ++g) {
-      offs[g] = total;
-      cnt[g] = static_cast<int>(groups[g].size());
-      std::copy(groups[g].begin(), groups[g].end(), hi + total);
-      total += cnt[g];
-    }
-    ZeroSeg* hz = h_zero_[slot];
-    int nz = 0;
-    for (const serve::Request* r : plan.zero) {
-      const int64_t count = r->tensor->dim * (r->tensor->kind == 0 ? 1 : r->R);
-      for (int64_t o = 0; o < count; o += kZeroPiece)
-        hz[nz++] = ZeroSeg{r->out + o, std::min(kZeroPiece, count - o)};
-    }
-    hipError_t e = hipSuccess;
-    if (total)
-      e = hipMemcpyAsync(d_items_[slot], hi, total * sizeof(ServeItem), hipMemcpyHostToDevice, stream_);
-    if (e == hipSuccess && nz)
-      e = hipMemcpyAsync(d_zero_[slot], hz, nz * sizeof(ZeroSeg), hipMemcpyHostToDevice, stream_);
-    if (e != hipSuccess) {
-      *err = std::string("serving step copy: ") + hipGetErrorString(e);
-      return serve::kEdevice;
-    }
-    int rc;
-    {
-      LaunchTimer timer(stream_);
-      // copies and zeroing on the first stream; everything else after them
-      rc = launch_serve_zero(d_zero_[slot], nz, d_counter_[slot], stream_);
-      if (!rc) rc = check_hip(hipEventRecord(evz_[slot], stream_), "hipEventRecord");
-      // MTTKRP items of order 3, 4, 5 on their own streams, so that the
-      // persistent kernels of a step overlap instead of draining one by one
-      for (int g = 1; g < 4 && !rc; ++g) {
-        hipStream_t ms = mstream_[g - 1];
-        rc = check_hip(hipStreamWaitEvent(ms, evz_[slot], 0), "hipStreamWaitEvent");
-        if (!rc)
-          rc = launch_serve_items(g + 2, d_items_[slot] + offs[g], cnt[g], d_counter_[slot] + g,
-                                  std::min(grid2_, std::max(1, cnt[g])), ms);
-        if (!rc) rc = check_hip(hipEventRecord(mev_[slot][g - 1], ms), "hipEventRecord");
-      }
-      if (!rc)
-        rc = launch_serve_items(0, d_items_[slot], cnt[0], d_counter_[slot],
-                                std::min(grid_, std::max(1, cnt[0])), stream_);
-    }
-    if (rc) {
-      *err = systec_last_error();
-      return rc;
-    }
-    e = hipEventRecord(ev_[slot], stream_);
-    if (e != hipSuccess) {
-      *err = std::string("serving step event: ") + hipGetErrorString(e);
-      return serve::kEdevice;
-    }
-    slot_step_[slot] = plan.step_id;
-    return serve::kOk;
-  }
-
-  int query(int64_t step_id, std::string* err) {
-    const int slot = static_cast<int>(step_id % kRing);
-    for (hipEvent_t ev : {ev_[slot], mev_[slot][0], mev_[slot][1], mev_[slot][2]}) {
-      const hipError_t e = hipEventQuery(ev);
-      if (e == hipErrorNotReady) return 0;
-      if (e != hipSuccess) {
-        *err = std::string("serving step failed: ") + hipGetErrorString(e);
-        return -1;
-      }
-    }
-    return 1;
-  }
-
-  void release(serve::TensorEntry& t) {
-    tensor_free(static_cast<Tensor*>(t.payload));
-    t.payload = nullptr;
-  }
-
-  hipStream_t stream() const { return stream_; }
-
- private:
-  int device_ = 0;
-  int grid_ = 512, grid2_ = 2048;
-  hipStream_t stream_ = nullptr;
-  hipStream_t mstream_[3] = {nullptr, nullptr, nullptr};
-  ServeItem* h_items_[kRing] = {};
-  ZeroSeg* h_zero_[kRing] = {};
-  ServeItem* d_items_[kRing] = {};
-  ZeroSeg* d_zero_[kRing] = {};
-  int* d_counter_[kRing] = {};
-  hipEvent_t ev_[kRing] = {}, evz_[kRing] = {};
-  hipEvent_t mev_[kRing][3] = {};
-  int64_t slot_step_[kRing] = {-1, -1, -1, -1};
-};
 
 // Work units of a prepared operand: SSYMV chunks, MTTKRP view ranges.
 void make_units(const Tensor* t, std::vector<serve::Unit>* units) {
@@ -246,6 +51,226 @@ void make_units(const Tensor* t, std::vector<serve::Unit>* units) {
       }
   }
 }
+
+class GpuExecutor {
+ public:
+  int init(int device, std::string* err) {
+    device_ = device;
+    hipError_t e = hipSetDevice(device);
+    for (int k = 0; k < 4 && e == hipSuccess; ++k)
+      e = hipStreamCreateWithFlags(&streams_[k], hipStreamNonBlocking);
+    stream_ = streams_[0];
+    int cus = 0;
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+    // persistent grids: as many workgroups as are resident at once
+    for (int k = 0; k < 4 && e == hipSuccess; ++k)
+      for (int v = 0; v < kStepVariants && e == hipSuccess; ++v) {
+        int per_cu = 0;
+        if (serve_blocks_per_cu(k == 0 ? 0 : k + 2, v, &per_cu) != SYSTEC_OK) e = hipErrorInvalidValue;
+        grid_[k][v] = std::max(1, cus) * std::max(1, per_cu);
+      }
+    // one counter set per (stream, variant)
+    if (e == hipSuccess)
+      e = hipMalloc(reinterpret_cast<void**>(&d_ctr_), 4 * kStepVariants * sizeof(StepCounter));
+    for (int i = 0; i < kRing && e == hipSuccess; ++i)
+      for (int k = 0; k < 4 && e == hipSuccess; ++k)
+        e = hipEventCreateWithFlags(&ev_[i][k], hipEventDisableTiming);
+    if (e != hipSuccess) {
+      *err = std::string("serving executor init: ") + hipGetErrorString(e);
+      return serve::kEdevice;
+    }
+    return serve::kOk;
+  }
+
+  ~GpuExecutor() {
+    for (hipStream_t st : streams_)
+      if (st) (void)hipStreamSynchronize(st);
+    for (auto& evs : ev_)
+      for (hipEvent_t ev : evs)
+        if (ev) (void)hipEventDestroy(ev);
+    for (hipStream_t st : streams_)
+      if (st) (void)hipStreamDestroy(st);
+    if (d_ctr_) (void)hipFree(d_ctr_);
+  }
+
+  // Builds the device descriptor and the unit table of an operand being
+  // registered (owned by the operand, freed with it).
+  int prepare(Tensor* t, std::vector<serve::Unit>* units, std::string* err) {
+    make_units(t, units);
+    std::vector<ServeUnit> hu(std::max<size_t>(1, units->size()));
+    for (size_t k = 0; k < units->size(); ++k)
+      hu[k] = ServeUnit{(*units)[k].a, (*units)[k].b, (*units)[k].c, 0};
+    ServeTensor d{};
+    d.kind = t->kind;
+    d.order = t->order;
+    d.dim = static_cast<int32_t>(t->dim);
+    d.H = t->panel_rows;
+    if (t->kind == 0) {
+      d.p[0][0] = t->pcol;
+      d.p[0][1] = t->prow;
+      d.p[0][2] = t->pval;
+    } else {
+      for (int v = 0; v < t->order; ++v) {
+        for (int q = 0; q < t->order; ++q) d.p[v][q] = t->vidx[v][q];
+        d.val[v] = t->vval[v];
+      }
+    }
+    (void)hipSetDevice(device_);
+    void *pu = nullptr, *pd = nullptr;
+    hipError_t e = hipMalloc(&pu, hu.size() * sizeof(ServeUnit));
+    if (e == hipSuccess) {
+      t->allocations.push_back(pu);
+      t->bytes += hu.size() * sizeof(ServeUnit);
+      e = hipMalloc(&pd, sizeof(ServeTensor));
+    }
+    if (e == hipSuccess) {
+      t->allocations.push_back(pd);
+      t->bytes += sizeof(ServeTensor);
+      d.units = static_cast<const ServeUnit*>(pu);
+      e = hipMemcpy(pu, hu.data(), hu.size() * sizeof(ServeUnit), hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess) e = hipMemcpy(pd, &d, sizeof(ServeTensor), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      *err = std::string("serving registration: ") + hipGetErrorString(e);
+      return serve::kEdevice;
+    }
+    t->d_units = static_cast<ServeUnit*>(pu);
+    t->d_serve = static_cast<ServeTensor*>(pd);
+    return serve::kOk;
+  }
+
+  uint64_t request_bytes(const serve::TensorEntry& t, int dtype, int64_t R) const {
+    const uint64_t es = dtype == SYSTEC_BF16 ? 2 : 4;
+    const uint64_t cols = t.kind == 0 ? 1 : static_cast<uint64_t>(R);
+    return static_cast<uint64_t>(t.dim) * cols * (es + 4);  // input + FP32 output
+  }
+
+  int launch(const serve::Plan& plan, std::string* err) {
+    (void)hipSetDevice(device_);
+    const int slot = static_cast<int>(plan.step_id % kRing);
+    // the slot's previous step has completed (fewer than kRing steps in flight)
+
+    // each request's share of the step: a contiguous range of its units
+    struct Share {
+      const serve::Request* req;
+      const Tensor* t;
+      int32_t unit0, count;
+    };
+    // (a request taken in both passes of the fill has two adjacent ranges)
+    std::vector<Share> shares;
+    for (const serve::PlanItem& pi : plan.items) {
+      const auto u0 = static_cast<int32_t>(pi.unit0);
+      const auto n = static_cast<int32_t>(pi.count);
+      auto it = std::find_if(shares.begin(), shares.end(),
+                             [&](const Share& sh) { return sh.req == pi.req; });
+      if (it == shares.end()) {
+        shares.push_back(Share{pi.req, static_cast<const Tensor*>(pi.tensor->payload), u0, n});
+      } else {
+        it->unit0 = std::min(it->unit0, u0);
+        it->count += n;
+      }
+    }
+
+    int rc = SYSTEC_OK;
+    {
+      LaunchTimer timer(stream_);
+      // one stream per kernel kind (SSYMV; MTTKRP of order 3, 4, 5): the
+      // outputs of the kind's newly admitted requests are zeroed on that
+      // stream, then its step kernel runs; the kinds overlap
+      for (int g = 0; g < 4 && !rc; ++g) {
+        hipStream_t st = streams_[g];
+        auto kind_of = [](const Tensor* t) { return t->kind == 0 ? 0 : t->order - 2; };
+        // outputs to zero, in batches of kStepReqs; each prologue also resets the
+        // stream's work queues, and one runs before every step launch
+        std::vector<ZeroArgs> zero;
+        for (size_t k = 0; k < plan.zero.size(); ++k) {
+          const serve::Request* r = plan.zero[k];
+          if (kind_of(static_cast<const Tensor*>(r->tensor->payload)) != g) continue;
+          if (zero.empty() || zero.back().n == kStepReqs) zero.push_back(ZeroArgs{});
+          ZeroArgs& z = zero.back();
+          z.ptr[z.n] = r->out;
+          z.count[z.n] = r->tensor->dim * (r->tensor->kind == 0 ? 1 : r->R);
+          ++z.n;
+        }
+        // the last zero batch goes with the first prologue before a step
+        // launch; every prologue resets all counter sets of the stream
+        StepCounter* ctr = d_ctr_ + g * kStepVariants;
+        size_t zi = 0;
+        auto prologue = [&]() {
+          const ZeroArgs z = zi < zero.size() ? zero[zi++] : ZeroArgs{};
+          return launch_serve_prologue(z, ctr, kStepVariants, st);
+        };
+        while (!rc && zi + 1 < zero.size()) rc = prologue();
+        bool fresh = false;  // counters reset since the last launch of each variant
+        for (int v = 0; v < kStepVariants && !rc; ++v) {
+          StepArgs a{};
+          bool first_batch = true;
+          auto launch_step = [&]() {
+            int r = SYSTEC_OK;
+            if (!fresh || !first_batch) r = prologue();  // another batch of this variant
+            fresh = true;
+            first_batch = false;
+            if (!r) r = launch_serve_step(g == 0 ? 0 : g + 2, v, a, grid_[g][v], ctr + v, st);
+            a = StepArgs{};
+            return r;
+          };
+          for (size_t k = 0; k < shares.size() && !rc; ++k) {
+            const Share& sh = shares[k];
+            if (kind_of(sh.t) != g) continue;
+            if (g > 0 && step_variant(sh.req->dtype, sh.req->R) != v) continue;
+            if (g == 0 && v != 0) continue;
+            StepReq& q = a.req[a.nreq++];
+            q.t = sh.t->d_serve;
+            q.in = sh.req->in;
+            q.out = sh.req->out;
+            q.unit0 = sh.unit0;
+            q.item0 = a.nitems;
+            q.R = static_cast<int32_t>(sh.req->R);
+            q.dtype = sh.req->dtype;
+            a.nitems += sh.count;
+            if (a.nreq == kStepReqs) rc = launch_step();
+          }
+          if (!rc && a.nreq) rc = launch_step();
+        }
+        while (!rc && zi < zero.size()) rc = prologue();  // outputs with no work this step
+        if (!rc) rc = check_hip(hipEventRecord(ev_[slot][g], st), "hipEventRecord");
+      }
+    }
+    if (rc) {
+      *err = systec_last_error();
+      return rc;
+    }
+    return serve::kOk;
+  }
+
+  int query(int64_t step_id, std::string* err) {
+    const int slot = static_cast<int>(step_id % kRing);
+    for (hipEvent_t ev : ev_[slot]) {
+      const hipError_t e = hipEventQuery(ev);
+      if (e == hipErrorNotReady) return 0;
+      if (e != hipSuccess) {
+        *err = std::string("serving step failed: ") + hipGetErrorString(e);
+        return -1;
+      }
+    }
+    return 1;
+  }
+
+  void release(serve::TensorEntry& t) {
+    tensor_free(static_cast<Tensor*>(t.payload));
+    t.payload = nullptr;
+  }
+
+  hipStream_t stream() const { return stream_; }
+
+ private:
+  int device_ = 0;
+  int grid_[4][kStepVariants] = {};  // per stream (SSYMV, MTTKRP order 3, 4, 5) and variant
+  StepCounter* d_ctr_ = nullptr;      // [stream][variant]
+  hipStream_t streams_[4] = {nullptr, nullptr, nullptr, nullptr};  // per kernel kind
+  hipStream_t stream_ = nullptr;                                   // streams_[0]
+  hipEvent_t ev_[kRing][4] = {};                                   // step done, per stream
+};
 
 }  // namespace
 }  // namespace systec
@@ -290,14 +315,19 @@ int systec_serve_register(systec_server* s, systec_tensor* t, int64_t* tensor_id
   if (!s || !t || !t->impl || !tensor_id)
     return serve_fail(SYSTEC_EINVAL, "systec_serve_register: NULL argument");
   auto e = std::make_shared<serve::TensorEntry>();
+  std::string err;
+  if (!t->impl->d_serve) {
+    const int prc = s->exec->prepare(t->impl, &e->units, &err);
+    if (prc) return serve_fail(prc, err);
+  } else {
+    make_units(t->impl, &e->units);
+  }
   e->kind = t->impl->kind;
   e->order = t->impl->order;
   e->dim = t->impl->dim;
   e->effective_nnz = t->impl->effective_nnz;
   e->bytes = t->impl->bytes;
   e->payload = t->impl;
-  make_units(t->impl, &e->units);
-  std::string err;
   const int rc = s->sched->register_tensor(e, tensor_id, &err);
   if (rc) return serve_fail(rc, err);
   t->impl = nullptr;  // ownership moved to the server

@@ -73,7 +73,8 @@ struct TensorEntry {
   int64_t effective_nnz = 0;
   uint64_t bytes = 0;
   std::vector<Unit> units;
-  void* payload = nullptr;  // executor-owned
+  std::vector<int64_t> unit_prefix;  // unit_prefix[k] = cost of units [0, k)
+  void* payload = nullptr;           // executor-owned
 };
 
 struct Request {
@@ -91,10 +92,11 @@ struct Request {
   std::string error;
 };
 
+// Units [unit0, unit0 + count) of a request's operand, run in one step.
 struct PlanItem {
   const TensorEntry* tensor;
-  const Unit* unit;
   const Request* req;
+  int64_t unit0, count;
 };
 
 struct Plan {
@@ -129,6 +131,9 @@ class Scheduler {
       *err = "registering the tensor would exceed the memory budget";
       return kEbudget;
     }
+    t->unit_prefix.assign(t->units.size() + 1, 0);
+    for (size_t k = 0; k < t->units.size(); ++k)
+      t->unit_prefix[k + 1] = t->unit_prefix[k] + std::max<int64_t>(1, t->units[k].cost);
     t->id = next_tensor_id_++;
     bytes_in_use_ += t->bytes;
     tensors_[t->id] = t;
@@ -325,32 +330,40 @@ class Scheduler {
   // alone). Every running request with work left gets at least one unit.
   void fill_locked(Plan& plan, std::vector<std::shared_ptr<Request>>& touched) {
     int64_t budget = cfg_.step_work;
-    auto take = [&](const std::shared_ptr<Request>& r, int64_t limit) {
-      const auto& units = r->tensor->units;
-      int64_t got = 0;
-      while (r->next_unit < units.size() && (got == 0 || got < limit) && budget > 0) {
-        const Unit& u = units[r->next_unit];
-        plan.items.push_back(PlanItem{r->tensor.get(), &u, r.get()});
-        got += u.cost;
-        budget -= u.cost;
-        ++r->next_unit;
+    // Takes the request's next units up to `limit` entries (and the step's
+    // remaining budget), the unit that crosses the limit included; with
+    // at_least_one, one unit even when the budget is spent.
+    auto take = [&](const std::shared_ptr<Request>& r, int64_t limit, bool at_least_one) {
+      const auto& pre = r->tensor->unit_prefix;
+      const size_t n = r->tensor->units.size();
+      const size_t first = r->next_unit;
+      if (first < n) {
+        const int64_t lim = std::min(limit, budget);
+        size_t end = first;
+        if (lim > 0)
+          end = static_cast<size_t>(
+              std::lower_bound(pre.begin() + first + 1, pre.end(), pre[first] + lim) - pre.begin());
+        if (at_least_one) end = std::max(end, first + 1);
+        end = std::min(end, n);
+        if (end > first) {
+          plan.items.push_back(PlanItem{r->tensor.get(), r.get(), static_cast<int64_t>(first),
+                                        static_cast<int64_t>(end - first)});
+          budget -= pre[end] - pre[first];
+          r->next_unit = end;
+          if (std::find(touched.begin(), touched.end(), r) == touched.end()) touched.push_back(r);
+        }
       }
-      if (got > 0 && std::find(touched.begin(), touched.end(), r) == touched.end())
-        touched.push_back(r);
-      if (r->next_unit == units.size() && r->last_step < 0) {
+      if (r->next_unit == n && r->last_step < 0) {
         r->last_step = plan.step_id;
         if (std::find(touched.begin(), touched.end(), r) == touched.end()) touched.push_back(r);
       }
     };
     const int64_t live = std::max<int64_t>(1, static_cast<int64_t>(active_.size()));
     const int64_t share = std::max<int64_t>(1, cfg_.step_work / (2 * live));
+    for (auto& r : active_) take(r, share, true);
     for (auto& r : active_) {
       if (budget <= 0) break;
-      take(r, share);
-    }
-    for (auto& r : active_) {
-      if (budget <= 0) break;
-      take(r, budget);
+      take(r, budget, false);
     }
     // requests whose operand has no units at all finish with this step
     for (auto& r : active_)

@@ -1,9 +1,20 @@
-// The serving step: persistent launches run the work items of every request
-// admitted to the step (continuous batching): one for the SSYMV items and one
-// for the MTTKRP items, on two streams so that they overlap. Workgroups pull
-// items through an atomic counter until the list is exhausted, so a step of
-// small items from many requests fills the device as well as one large
-// request. Each item runs the same device code as the standalone kernels.
+// The serving step: one launch per kernel kind runs the work of every request
+// admitted to the step (continuous batching): one for SSYMV and one per
+// MTTKRP order, on separate streams so that they overlap. The step's
+// requests and their unit ranges arrive as kernel arguments. The launches
+// are persistent: as many workgroups as fit on the device at once take items
+// from eight work queues until all are empty, and each item runs the same
+// device code as the standalone kernels.
+//
+// Work queues. Item i belongs to queue i mod 8; a queue is a counter that
+// hands out its items in order. Workgroup b starts on queue b mod 8 (blocks
+// are dispatched round-robin over the 8 XCDs, so a queue's items tend to stay
+// on one XCD) and moves on to the other queues when its own is empty. A
+// single counter serializes every workgroup of the chip on one address
+// (about 80 M atomics/s); eight counters on separate cache lines spread that
+// over eight. A prologue kernel on the same stream resets the counters
+// before every step launch, and zeroes the outputs of newly admitted
+// requests.
 #include "common.h"
 #include "mttkrp_device.h"
 #include "panel_device.h"
@@ -13,115 +24,211 @@ namespace {
 
 using namespace dev;
 
-// Zeroes the outputs of newly admitted requests, cut into pieces of at most
-// 16384 floats (one piece per workgroup iteration). Block 0 also resets the
-// step's four work counters (SSYMV items, MTTKRP items of order 3, 4, 5).
-__global__ void serve_zero_kernel(const ZeroSeg* __restrict__ segs, int nseg,
-                                  int* __restrict__ counters) {
-  if (blockIdx.x == 0 && threadIdx.x < 4) counters[threadIdx.x] = 0;
-  for (int b = blockIdx.x; b < nseg; b += gridDim.x) {
-    const ZeroSeg z = segs[b];
-    for (int64_t i = threadIdx.x; i < z.count; i += blockDim.x) z.ptr[i] = 0.0f;
+__global__ void serve_prologue_kernel(ZeroArgs z, StepCounter* ctr, int nsets) {
+  if (blockIdx.x == 0 && threadIdx.x < kStepQueues * nsets)
+    ctr[threadIdx.x / kStepQueues].next[(threadIdx.x % kStepQueues) * kQueueStride] = 0;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  const int64_t t0 = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  for (int s = 0; s < z.n; ++s) {
+    float* p = z.ptr[s];
+    const int64_t n = z.count[s];
+    if ((reinterpret_cast<uintptr_t>(p) & 15) == 0) {
+      float4* q = reinterpret_cast<float4*>(p);
+      const int64_t n4 = n / 4;
+      for (int64_t i = t0; i < n4; i += stride) q[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+      for (int64_t i = n4 * 4 + t0; i < n; i += stride) p[i] = 0.0f;
+    } else {
+      for (int64_t i = t0; i < n; i += stride) p[i] = 0.0f;
+    }
   }
 }
 
+// Values that are the same in every lane, moved to scalar registers (the
+// compiler cannot prove that loads through the step's descriptors are
+// uniform, and would otherwise keep every pointer in vector registers).
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+template <typename T>
+__device__ __forceinline__ T* uni_ptr(T* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v >> 32));
+  return reinterpret_cast<T*>((static_cast<uint64_t>(hi) << 32) | lo);
+}
+__device__ __forceinline__ ServeUnit load_unit(const ServeTensor* t, int k) {
+  const ServeUnit u = uni_ptr(t->units)[k];
+  return ServeUnit{uni(u.a), uni(u.b), uni(u.c), 0};
+}
+
+// The request that item i belongs to (item0 ascends; uniform across the
+// workgroup, so this runs on scalar registers).
+__device__ __forceinline__ int find_req(const StepArgs& a, int i) {
+  int r = 0;
+  for (int k = 1; k < a.nreq; ++k) r = (a.req[k].item0 <= i) ? k : r;
+  return r;
+}
+
+// One MTTKRP item is a range of a few tiles of one view; the waves of the
+// workgroup take every fourth tile.
 template <int N, typename BT, int L>
-__device__ __forceinline__ void view_range(const ServeItem& it) {
+__device__ __forceinline__ void view_range(const ServeTensor* t, const ServeUnit& u,
+                                           const StepReq& q) {
   IdxPtrs ip{};
 #pragma unroll
-  for (int q = 0; q < N; ++q) ip.p[q] = static_cast<const int32_t*>(it.p[q]);
-  const BT* B = static_cast<const BT*>(it.in);
+  for (int s = 0; s < N; ++s) ip.p[s] = uni_ptr(static_cast<const int32_t*>(t->p[u.a][s]));
+  const float* val = uni_ptr(t->val[u.a]);
+  const BT* B = static_cast<const BT*>(q.in);
   const int w = threadIdx.x / kWave, nw = blockDim.x / kWave;
-  for (int e0 = it.begin + w * kTileE; e0 < it.end; e0 += nw * kTileE)
-    mttkrp_view_tile<N, BT, L>(it.slot, e0, min(it.end, e0 + kTileE), ip, it.val, B, it.R, it.out,
-                               it.R, 0, it.R);
+  for (int e0 = u.b + w * kTileE; e0 < u.c; e0 += nw * kTileE)
+    mttkrp_view_tile_slot<N, BT, L>(u.a, e0, min(u.c, e0 + kTileE), ip, val, B, q.R, q.out, q.R,
+                                    0, q.R);
 }
 
-template <int N, typename BT>
-__device__ __forceinline__ void view_item(const ServeItem& it) {
-  if (it.R <= 8) view_range<N, BT, 8>(it);
-  else if (it.R <= 16) view_range<N, BT, 16>(it);
-  else if (it.R <= 32) view_range<N, BT, 32>(it);
-  else view_range<N, BT, 64>(it);
-}
-
-// Persistent step kernels: workgroups pull items through an atomic counter
-// until the list is exhausted (every workgroup reaches the same exit).
-// SSYMV panel chunks need the panel's row sums in LDS (512 threads, 64 KiB);
-// MTTKRP view ranges need no LDS and run at full occupancy (256 threads, one
-// kernel per tensor order so that each keeps the registers of its own order).
-__device__ __forceinline__ int next_item(int* counter, int* s_next) {
-  if (threadIdx.x == 0) *s_next = atomicAdd(counter, 1);
+// Takes this workgroup's next item (uniform across the workgroup), or
+// returns n when every queue is empty. `q` is the queue being drained.
+__device__ __forceinline__ int take_item(StepCounter* c, int n, int* q, int* s_item) {
+  if (threadIdx.x == 0) {
+    int item = n;
+    for (int k = 0; k < kStepQueues; ++k) {
+      const int qq = (*q + k) & (kStepQueues - 1);
+      int* ctr = c->next + qq * kQueueStride;
+      // skip a drained queue without contending for its counter
+      if (k > 0 && __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) * kStepQueues +
+                           qq >= n)
+        continue;
+      const int i = atomicAdd(ctr, 1) * kStepQueues + qq;
+      if (i < n) {
+        item = i;
+        *q = qq;
+        break;
+      }
+    }
+    *s_item = item;
+  }
   __syncthreads();
-  // the same for every lane: make that visible so the item is read with
-  // scalar loads into SGPRs instead of occupying vector registers
-  const int i = __builtin_amdgcn_readfirstlane(*s_next);
+  const int i = uni(*s_item);
   __syncthreads();
   return i;
 }
 
-__global__ __launch_bounds__(kServeBlock) void serve_ssymv_kernel(const ServeItem* __restrict__ items,
-                                                                int nitems,
-                                                                int* __restrict__ counter) {
+// SSYMV items need the panel's row sums in LDS (512 threads, 64 KiB); MTTKRP
+// items need no LDS and run at full occupancy (256 threads, one kernel per
+// tensor order so that each keeps the registers of its own order); the four
+// waves of an MTTKRP workgroup share an item of a few tiles each.
+__global__ __launch_bounds__(kServeBlock) void serve_ssymv_kernel(StepArgs a, StepCounter* ctr) {
   extern __shared__ float s_lds[];
-  __shared__ int s_next;
-  for (;;) {
-    const int i = next_item(counter, &s_next);
-    if (i >= nitems) return;  // uniform across the workgroup
-    const ServeItem it = items[i];
-    const auto* pcol = static_cast<const int32_t*>(it.p[0]);
-    const auto* prow = static_cast<const uint16_t*>(it.p[1]);
-    const auto* pval = static_cast<const float*>(it.p[2]);
-    if (it.dtype == SYSTEC_F32)
-      ssymv_panel_chunk<float>(it.dim, it.H, it.panel, it.begin, it.end, pcol, prow, pval,
-                               static_cast<const float*>(it.in), it.out, s_lds);
+  __shared__ int s_item;
+  int q = blockIdx.x & (kStepQueues - 1);
+  for (int i = take_item(ctr, a.nitems, &q, &s_item); i < a.nitems;
+       i = take_item(ctr, a.nitems, &q, &s_item)) {
+    const StepReq& r = a.req[find_req(a, i)];
+    const ServeTensor* t = r.t;
+    const ServeUnit u = load_unit(t, r.unit0 + (i - r.item0));
+    const auto* pcol = uni_ptr(static_cast<const int32_t*>(t->p[0][0]));
+    const auto* prow = uni_ptr(static_cast<const uint16_t*>(t->p[0][1]));
+    const auto* pval = uni_ptr(static_cast<const float*>(t->p[0][2]));
+    const int dim = uni(t->dim), H = uni(t->H);
+    if (r.dtype == SYSTEC_F32)
+      ssymv_panel_chunk<float>(dim, H, u.a, u.b, u.c, pcol, prow, pval,
+                               static_cast<const float*>(r.in), r.out, s_lds);
     else
-      ssymv_panel_chunk<uint16_t>(it.dim, it.H, it.panel, it.begin, it.end, pcol, prow, pval,
-                                  static_cast<const uint16_t*>(it.in), it.out, s_lds);
-    __syncthreads();
+      ssymv_panel_chunk<uint16_t>(dim, H, u.a, u.b, u.c, pcol, prow, pval,
+                                  static_cast<const uint16_t*>(r.in), r.out, s_lds);
+  }
+}
+
+// One MTTKRP step kernel per (order, factor dtype, lane group width), so that
+// each keeps only the registers of its own variant.
+template <int N, typename BT, int L>
+__global__ __launch_bounds__(kServeMttkrpBlock) void serve_mttkrp_kernel(StepArgs a,
+                                                                         StepCounter* ctr) {
+  __shared__ int s_item;
+  int q = blockIdx.x & (kStepQueues - 1);
+  for (int i = take_item(ctr, a.nitems, &q, &s_item); i < a.nitems;
+       i = take_item(ctr, a.nitems, &q, &s_item)) {
+    const StepReq& r = a.req[find_req(a, i)];
+    const ServeTensor* t = r.t;
+    const ServeUnit u = load_unit(t, r.unit0 + (i - r.item0));
+    view_range<N, BT, L>(t, u, r);
+  }
+}
+
+// The kernel of a (kind, variant) pair: kind 0 is SSYMV; kinds 3, 4, 5 are
+// MTTKRP of that order with variant = 4 * (dtype is BF16) + lane class
+// (L = 8, 16, 32, 64).
+template <int N>
+const void* mttkrp_kernel_of(int variant) {
+  const bool bf16 = variant >= 4;
+  switch (variant & 3) {
+    case 0: return bf16 ? reinterpret_cast<const void*>(serve_mttkrp_kernel<N, uint16_t, 8>)
+                        : reinterpret_cast<const void*>(serve_mttkrp_kernel<N, float, 8>);
+    case 1: return bf16 ? reinterpret_cast<const void*>(serve_mttkrp_kernel<N, uint16_t, 16>)
+                        : reinterpret_cast<const void*>(serve_mttkrp_kernel<N, float, 16>);
+    case 2: return bf16 ? reinterpret_cast<const void*>(serve_mttkrp_kernel<N, uint16_t, 32>)
+                        : reinterpret_cast<const void*>(serve_mttkrp_kernel<N, float, 32>);
+    default: return bf16 ? reinterpret_cast<const void*>(serve_mttkrp_kernel<N, uint16_t, 64>)
+                         : reinterpret_cast<const void*>(serve_mttkrp_kernel<N, float, 64>);
   }
 }
 
 template <int N>
-__global__ __launch_bounds__(kServeMttkrpBlock, 7) void serve_mttkrp_kernel(
-    const ServeItem* __restrict__ items, int nitems, int* __restrict__ counter) {
-  __shared__ int s_next;
-  for (;;) {
-    const int i = next_item(counter, &s_next);
-    if (i >= nitems) return;
-    const ServeItem it = items[i];
-    if (it.dtype == SYSTEC_F32) view_item<N, float>(it);
-    else view_item<N, uint16_t>(it);
+void launch_mttkrp_variant(int variant, const StepArgs& a, dim3 g, StepCounter* ctr, hipStream_t s) {
+  const bool bf16 = variant >= 4;
+  const dim3 b(kServeMttkrpBlock);
+  switch (variant & 3) {
+    case 0:
+      if (bf16) serve_mttkrp_kernel<N, uint16_t, 8><<<g, b, 0, s>>>(a, ctr);
+      else serve_mttkrp_kernel<N, float, 8><<<g, b, 0, s>>>(a, ctr);
+      break;
+    case 1:
+      if (bf16) serve_mttkrp_kernel<N, uint16_t, 16><<<g, b, 0, s>>>(a, ctr);
+      else serve_mttkrp_kernel<N, float, 16><<<g, b, 0, s>>>(a, ctr);
+      break;
+    case 2:
+      if (bf16) serve_mttkrp_kernel<N, uint16_t, 32><<<g, b, 0, s>>>(a, ctr);
+      else serve_mttkrp_kernel<N, float, 32><<<g, b, 0, s>>>(a, ctr);
+      break;
+    default:
+      if (bf16) serve_mttkrp_kernel<N, uint16_t, 64><<<g, b, 0, s>>>(a, ctr);
+      else serve_mttkrp_kernel<N, float, 64><<<g, b, 0, s>>>(a, ctr);
+      break;
   }
 }
 
 }  // namespace
 
-int launch_serve_zero(const ZeroSeg* d_zero, int nzero, int* d_counters, hipStream_t s) {
-  const int zgrid = std::max(1, std::min(nzero, 8192));
-  serve_zero_kernel<<<dim3(zgrid), dim3(256), 0, s>>>(d_zero, nzero, d_counters);
-  return check_launch("serve zero kernel");
+int launch_serve_prologue(const ZeroArgs& z, StepCounter* ctr, int nsets, hipStream_t s) {
+  int64_t total = 0;
+  for (int k = 0; k < z.n; ++k) total += z.count[k];
+  const int grid = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>((total / 4 + 255) / 256, 2048)));
+  serve_prologue_kernel<<<dim3(grid), dim3(256), 0, s>>>(z, ctr, nsets);
+  return check_launch("serve prologue kernel");
 }
 
-int launch_serve_items(int kind, const ServeItem* d_items, int nitems, int* d_counter, int grid,
-                       hipStream_t s) {
-  if (nitems == 0) return SYSTEC_OK;
-  const dim3 g(std::max(1, grid));
+int launch_serve_step(int kind, int variant, const StepArgs& a, int grid, StepCounter* ctr,
+                      hipStream_t s) {
+  if (a.nitems == 0) return SYSTEC_OK;
+  const dim3 g(std::max(1, std::min(grid, a.nitems)));
   switch (kind) {
-    case 0:
-      serve_ssymv_kernel<<<g, dim3(kServeBlock), kServeLds, s>>>(d_items, nitems, d_counter);
-      break;
-    case 3:
-      serve_mttkrp_kernel<3><<<g, dim3(kServeMttkrpBlock), 0, s>>>(d_items, nitems, d_counter);
-      break;
-    case 4:
-      serve_mttkrp_kernel<4><<<g, dim3(kServeMttkrpBlock), 0, s>>>(d_items, nitems, d_counter);
-      break;
-    default:
-      serve_mttkrp_kernel<5><<<g, dim3(kServeMttkrpBlock), 0, s>>>(d_items, nitems, d_counter);
-      break;
+    case 0: serve_ssymv_kernel<<<g, dim3(kServeBlock), kServeLds, s>>>(a, ctr); break;
+    case 3: launch_mttkrp_variant<3>(variant, a, g, ctr, s); break;
+    case 4: launch_mttkrp_variant<4>(variant, a, g, ctr, s); break;
+    default: launch_mttkrp_variant<5>(variant, a, g, ctr, s); break;
   }
   return check_launch(kind == 0 ? "serve ssymv kernel" : "serve mttkrp kernel");
+}
+
+int serve_blocks_per_cu(int kind, int variant, int* blocks) {
+  hipError_t e;
+  if (kind == 0) {
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, serve_ssymv_kernel, kServeBlock,
+                                                     kServeLds);
+  } else {
+    const void* k = kind == 3 ? mttkrp_kernel_of<3>(variant)
+                    : kind == 4 ? mttkrp_kernel_of<4>(variant)
+                                : mttkrp_kernel_of<5>(variant);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k, kServeMttkrpBlock, 0);
+  }
+  return check_hip(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
 }
 
 }  // namespace systec

@@ -46,10 +46,12 @@ struct FakeExec {
     plans.push_back(p);
     std::vector<int64_t> ids;
     for (auto& it : p.items) {
-      const size_t ui = it.unit - it.tensor->units.data();
-      auto key = std::make_pair(it.req->id, ui);
-      CHECK(done_units.insert(key).second);  // every unit runs exactly once
-      ids.push_back(it.req->id);
+      CHECK(it.count >= 1);
+      for (int64_t k = 0; k < it.count; ++k) {
+        auto key = std::make_pair(it.req->id, static_cast<size_t>(it.unit0 + k));
+        CHECK(done_units.insert(key).second);  // every unit runs exactly once
+        ids.push_back(it.req->id);
+      }
       running_bytes[it.req->id] = it.req->bytes;
     }
     for (auto* z : p.zero) running_bytes[z->id] = z->bytes;
@@ -312,12 +314,48 @@ void test_concurrent_submitters() {
   std::printf("PASS concurrent_submitters\n");
 }
 
+
+void test_every_running_request_progresses() {
+  // a step budget smaller than one unit: each running request still gets a
+  // unit in every step, so a small request that joins a long one finishes
+  // first instead of waiting for the long one to drain
+  FakeExec ex;
+  ex.delay_us = 200;
+  Config c;
+  c.budget_bytes = 1 << 30;
+  c.max_slots = 4;
+  c.step_work = 1;
+  Scheduler<FakeExec> s(c, ex);
+  int64_t big_t, small_t, big, small;
+  std::string err;
+  CHECK(s.register_tensor(tensor(1, 10, 200, 100), &big_t, &err) == kOk);
+  CHECK(s.register_tensor(tensor(1, 10, 3, 100), &small_t, &err) == kOk);
+  CHECK(s.submit(big_t, &ex, 0, 1, nullptr, 0, &big, &err) == kOk);
+  std::this_thread::sleep_for(std::chrono::milliseconds(2));
+  CHECK(s.submit(small_t, &ex, 0, 1, nullptr, 0, &small, &err) == kOk);
+  CHECK(s.wait(small, 20000000, &err) == kOk);
+  int state = -1;
+  CHECK(s.poll(big, &state) == kOk && state == kRunning);
+  CHECK(s.wait(big, 20000000, &err) == kOk);
+  {
+    std::lock_guard<std::mutex> lk(ex.mu);
+    for (auto& ids : ex.step_reqs) {
+      bool hb = false, hs = false;
+      for (auto q : ids) hb |= q == big, hs |= q == small;
+      CHECK(!hs || hb);  // the small request shared its steps with the big one
+      CHECK(ids.size() <= 2);
+    }
+  }
+  std::printf("PASS every_running_request_progresses\n");
+}
+
 int main() {
   test_percentiles();
   test_basic_all_units_once();
   test_budget_and_slots();
   test_budget_blocks_then_resumes();
   test_fifo_and_continuous_batching();
+  test_every_running_request_progresses();
   test_failure_and_timeout();
   test_shutdown_cancels_queue();
   test_concurrent_submitters();

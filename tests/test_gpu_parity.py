@@ -139,14 +139,14 @@ def test_full_csr_comparison_kernel():
 
 # ------------------------------------------------------------------ MTTKRP --
 
-def _mttkrp(t, B, bdtype="f32"):
+def _mttkrp(t, B, bdtype="f32", algo="auto"):
     idx = [dev(a) for a in t["idx"]]
     val = dev(t["val"].astype(np.float32))
     if bdtype == "f32":
         Bd = dev(B.astype(np.float32))
     else:
         Bd = systec.quantize_bf16(dev(B.astype(np.float32)))
-    return systec.mttkrp(idx, val, Bd).cpu().numpy()
+    return systec.mttkrp(idx, val, Bd, algo=algo).cpu().numpy()
 
 
 def _oracle_mttkrp(t, B, bdtype="f32", row_mask=None):
@@ -159,10 +159,11 @@ def _oracle_mttkrp(t, B, bdtype="f32", row_mask=None):
 @pytest.mark.parametrize("R", [1, 8, 16, 17, 32, 64, 100])
 @pytest.mark.parametrize("bdtype", ["f32", "bf16"])
 def test_mttkrp_matches_oracle(order, dim, nnz, R, bdtype):
+    algo = "atomic"
     t = synth.sym_coo(order, dim, nnz, repeat_frac=0.2, seed=1000 + order * 7 + R)
     B = synth.dense_uniform((dim, R), seed=R)
-    print(f"mttkrp order={order} dim={dim} nnz={nnz} R={R} B={bdtype}", flush=True)
-    C = _mttkrp(t, B, bdtype)
+    print(f"mttkrp order={order} dim={dim} nnz={nnz} R={R} B={bdtype} algo={algo}", flush=True)
+    C = _mttkrp(t, B, bdtype, algo)
     want, counts = _oracle_mttkrp(t, B, bdtype)
     assert all(h > 0 for h in counts["hist"])  # every equality pattern present
     assert rel_err(C, want) <= TOL32
@@ -172,24 +173,26 @@ def test_mttkrp_matches_oracle(order, dim, nnz, R, bdtype):
 
 
 @pytest.mark.parametrize("order", [3, 4, 5])
-def test_mttkrp_all_diagonal_and_empty(order):
+@pytest.mark.parametrize("algo", ["atomic", "auto"])
+def test_mttkrp_all_diagonal_and_empty(order, algo):
     import torch
     dim, R = 700, 16
     diag = {"order": order, "dim": dim,
             "idx": np.stack([np.arange(dim, dtype=np.int32)] * order),
             "val": synth.dense_uniform(dim, seed=5)}
     B = synth.dense_uniform((dim, R), seed=6)
-    C = _mttkrp(diag, B)
+    C = _mttkrp(diag, B, algo=algo)
     want, _ = _oracle_mttkrp(diag, B)
     assert rel_err(C, want) <= TOL32
     empty = [torch.empty(0, dtype=torch.int32, device="cuda") for _ in range(order)]
     Ce = systec.mttkrp(empty, torch.empty(0, device="cuda"), dev(B.astype(np.float32)),
-                       out=torch.full((dim, R), 3.0, device="cuda"))
+                       out=torch.full((dim, R), 3.0, device="cuda"), algo=algo)
     assert torch.count_nonzero(Ce).item() == 0
 
 
 @pytest.mark.parametrize("order", [3, 5])
 def test_mttkrp_long_leading_run(order):
+    algo = "atomic"
     # every entry shares c1 = 0: one register-accumulated run across tiles
     dim = 40 if order == 3 else 14
     rest = np.array(list(itertools.combinations_with_replacement(range(dim), order - 1)),
@@ -199,33 +202,29 @@ def test_mttkrp_long_leading_run(order):
          "val": synth.dense_uniform(idx.shape[0], seed=8)}
     B = synth.dense_uniform((dim, 32), seed=9)
     assert idx.shape[0] > 512
-    assert rel_err(_mttkrp(t, B), _oracle_mttkrp(t, B)[0]) <= TOL32
+    assert rel_err(_mttkrp(t, B, algo=algo), _oracle_mttkrp(t, B)[0]) <= TOL32
 
 
 def test_mttkrp_order_invariance():
+    algo = "auto"
     # the kernel does not rely on the list order for correctness
     t = synth.sym_coo(4, 200, 30000, 0.05, seed=77)
     B = synth.dense_uniform((200, 16), seed=78)
-    C0 = _mttkrp(t, B)
+    C0 = _mttkrp(t, B, algo=algo)
     perm = np.random.Generator(np.random.PCG64(79)).permutation(30000)
     ts = dict(t, idx=np.ascontiguousarray(t["idx"][:, perm]), val=t["val"][perm])
-    C1 = _mttkrp(ts, B)
+    C1 = _mttkrp(ts, B, algo=algo)
     assert rel_err(C1, C0) <= TOL32
 
 
-@pytest.mark.parametrize("order", [3, 4, 5])
-def test_full_coo_comparison_kernel(order):
-    t = synth.sym_coo(order, 80, 6000, 0.1, seed=90 + order)
-    B = synth.dense_uniform((80, 16), seed=91)
-    idx = [dev(a) for a in t["idx"]]
-    val = dev(t["val"].astype(np.float32))
-    fidx, fval = systec.expand_coo(idx, val, 80)
-    want, counts = _oracle_mttkrp(t, B)
-    assert fval.numel() == counts["effective_nnz"]
-    first = fidx[0].cpu().numpy()
-    assert np.all(np.diff(first) >= 0)  # grouped by the output index
-    C = systec.mttkrp_full(fidx, fval, dev(B.astype(np.float32))).cpu().numpy()
-    assert rel_err(C, want) <= TOL32
+def test_mttkrp_oneshot_rejects_prepared_algorithms():
+    t = synth.sym_coo(3, 50, 1000, 0.0, seed=5)
+    B = dev(synth.dense_uniform((50, 8), seed=6).astype(np.float32))
+    for algo in ("views", "lds"):
+        with pytest.raises(systec.SystecError) as e:
+            systec.mttkrp([dev(a) for a in t["idx"]], dev(t["val"].astype(np.float32)), B,
+                          algo=algo)
+        assert e.value.status_name == "SYSTEC_EINVAL"
 
 
 # ---------------------------------------------------------- integer parts --

@@ -95,7 +95,8 @@ def test_prepared_rejects_noncanonical():
 @pytest.mark.parametrize("order,dim,nnz", [(3, 400, 30011), (4, 150, 20021), (5, 70, 12007)])
 @pytest.mark.parametrize("R", [1, 16, 32, 70])
 @pytest.mark.parametrize("bdtype", ["f32", "bf16"])
-def test_prepared_mttkrp(order, dim, nnz, R, bdtype):
+@pytest.mark.parametrize("algo", ["views", "lds", "atomic"])
+def test_prepared_mttkrp(order, dim, nnz, R, bdtype, algo):
     t = synth.sym_coo(order, dim, nnz, repeat_frac=0.2, seed=2000 + order * 11 + R)
     B = synth.dense_uniform((dim, R), seed=R + 1)
     T = systec.Tensor.from_coo([dev(a) for a in t["idx"]], dev(t["val"].astype(np.float32)), dim)
@@ -104,7 +105,7 @@ def test_prepared_mttkrp(order, dim, nnz, R, bdtype):
     if bdtype == "bf16":
         Bd = systec.quantize_bf16(Bd)
         Bref = oracle.round_bf16(B.astype(np.float32))
-    C = T.mttkrp(Bd).cpu().numpy()
+    C = T.mttkrp(Bd, algo=algo).cpu().numpy()
     want, counts = oracle.mttkrp(order, dim, t["idx"].T, f32(t["val"]), Bref)
     assert rel_err(C, want) <= TOL32
     assert T.effective_nnz == counts["effective_nnz"]
@@ -121,6 +122,51 @@ def test_prepared_mttkrp_all_diagonal(order):
     C = T.mttkrp(dev(B.astype(np.float32))).cpu().numpy()
     want, _ = oracle.mttkrp(order, dim, idx.T, f32(val), f32(B))
     assert rel_err(C, want) <= TOL32
+
+
+@pytest.mark.parametrize("order,dim,R,bdtype", [
+    (5, 5000, 16, "bf16"),    # the 5-D workload's shape: one 16-column slice
+    (3, 10000, 8, "bf16"),    # near the LDS limit: one 8-column slice
+    (4, 9000, 3, "f32"),      # FP32 B, ragged slice (4 columns, 3 used)
+    (3, 2000, 100, "bf16"),   # two 64-column slices, ragged last slice
+    (4, 600, 40, "f32"),      # FP32 B, one 64-column slice (40 used)
+    (5, 30, 16, "f32"),       # fewer entries than workgroups x lane groups
+])
+def test_prepared_mttkrp_lds_shapes(order, dim, R, bdtype):
+    nnz = {5000: 200003, 10000: 150001, 9000: 120007, 2000: 50021, 600: 40009, 30: 3001}[dim]
+    t = synth.sym_coo(order, dim, nnz, repeat_frac=0.05, seed=2000 + dim)
+    B = synth.dense_uniform((dim, R), seed=dim)
+    print(f"prepared mttkrp lds order={order} dim={dim} nnz={nnz} R={R} B={bdtype}", flush=True)
+    T = systec.Tensor.from_coo([dev(a) for a in t["idx"]], dev(t["val"].astype(np.float32)), dim)
+    Bd = dev(B.astype(np.float32))
+    Bref = f32(B)
+    if bdtype == "bf16":
+        Bd = systec.quantize_bf16(Bd)
+        Bref = oracle.round_bf16(B.astype(np.float32))
+    want, _ = oracle.mttkrp(order, dim, t["idx"].T, f32(t["val"]), Bref)
+    assert rel_err(T.mttkrp(Bd, algo="lds").cpu().numpy(), want) <= TOL32
+    assert rel_err(T.mttkrp(Bd, algo="views").cpu().numpy(), want) <= TOL32
+    T.close()
+
+
+def test_prepared_mttkrp_lds_rejects_large_index_space():
+    import torch
+    t = synth.sym_coo(3, 100000, 1000, 0.0, seed=5)
+    T = systec.Tensor.from_coo([dev(a) for a in t["idx"]], dev(t["val"].astype(np.float32)),
+                               100000)
+    Bh = synth.dense_uniform((100000, 16), seed=6)
+    B = dev(Bh.astype(np.float32))
+    with pytest.raises(systec.SystecError) as e:
+        T.mttkrp(B, algo="lds")
+    assert e.value.status_name == "SYSTEC_EINVAL"
+    assert systec.mttkrp_choose(100000, 16, False, True) == "views"
+    assert systec.mttkrp_choose(5000, 16, True, True) == "views"
+    assert systec.mttkrp_choose(5000, 16, True, False) == "atomic"
+    C = T.mttkrp(B)  # the automatic choice falls back to the views
+    torch.cuda.synchronize()
+    want, _ = oracle.mttkrp(3, 100000, t["idx"].T, f32(t["val"]), f32(Bh))
+    assert rel_err(C.cpu().numpy(), want) <= TOL32
+    T.close()
 
 
 def test_prepared_full_size_ssymv_rmat():
@@ -144,8 +190,10 @@ def test_prepared_full_size_mttkrp_sampled(name):
     mask = np.zeros(I, np.uint8)
     mask[rows] = 1
     Bd = systec.quantize_bf16(dev(t["B"].astype(np.float32)))
-    C = T.mttkrp(Bd).cpu().numpy()
     want, counts = oracle.mttkrp(t["order"], I, t["idx"].T, f32(t["val"]),
                                  oracle.round_bf16(t["B"].astype(np.float32)), row_mask=mask)
-    assert rel_err(C[rows], want[rows]) <= TOL32
+    algos = ["views", "atomic"] + (["lds"] if name == "mttkrp5" else [])
+    for algo in algos:  # the launch configurations the benchmark times
+        C = T.mttkrp(Bd, algo=algo).cpu().numpy()
+        assert rel_err(C[rows], want[rows]) <= TOL32, algo
     assert T.effective_nnz == counts["effective_nnz"]

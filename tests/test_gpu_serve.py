@@ -144,19 +144,41 @@ def test_small_budget_blocks_and_resumes():
 
 
 def test_arrivals_while_running_are_admitted():
+    """A long request runs; requests that arrive while it is on the GPU are
+    admitted into its steps and finish before it (each step gives every
+    running request at least one work unit); every result matches the same
+    request computed alone."""
+    import time
+    import torch
     mats, tens = _pool()
-    reqs = _requests(mats, tens, 40, seed=11)
-    with systec.Server(budget_bytes=8 << 30, max_slots=16, step_work_nnz=1 << 16) as srv:
+    reqs = _requests(mats, tens, 20, seed=11)
+    big = synth.gpu_sym_coo(3, 100_000, 20_000_000, 0.01, seed=12)
+    B = systec.quantize_bf16(torch.rand((100_000, 8), device="cuda") * 2 - 1)
+    alone = systec.Tensor.from_coo(big["idx"], big["val"], 100_000).mttkrp(B)
+    torch.cuda.synchronize()
+    with systec.Server(budget_bytes=16 << 30, max_slots=32, step_work_nnz=1) as srv:
         ids = _register(srv, mats, tens)
-        outs = []
-        for k, r in enumerate(reqs):
-            outs.append(_submit(srv, ids, mats, tens, r, True))
-            if k == 5:
-                assert any(srv.poll(rid) != srv.QUEUED for rid, _ in outs[:5])
+        bid = srv.register(systec.Tensor.from_coo(big["idx"], big["val"], 100_000))
+        del big
+        out_big = torch.empty((100_000, 8), device="cuda")
+        torch.cuda.synchronize()
+        rid_big = srv.submit(bid, B, out_big)
+        t0 = time.time()
+        while srv.poll(rid_big) == srv.QUEUED and time.time() - t0 < 30:
+            time.sleep(1e-4)
+        assert srv.poll(rid_big) == srv.RUNNING
+        outs = [_submit(srv, ids, mats, tens, r, True) for r in reqs]
+        done_while_big_ran = 0
+        while srv.poll(rid_big) == srv.RUNNING and time.time() - t0 < 60:
+            done_while_big_ran = sum(srv.poll(rid) == srv.DONE for rid, _ in outs)
+            time.sleep(2e-4)
         for rid, _ in outs:
             srv.wait(rid, 60_000_000)
+        srv.wait(rid_big, 60_000_000)
         st = srv.stats()
-    assert st["completed"] == 40 and st["steps"] >= 2
+    assert done_while_big_ran >= 1
+    assert st["completed"] == 21 and st["steps"] >= 2
+    assert rel_err(out_big.cpu().numpy(), alone.cpu().numpy()) <= TOL32
     for r, (_, o) in zip(reqs, outs):
         assert rel_err(o.cpu().numpy(), _oracle(mats, tens, r, True)) <= TOL32
 
