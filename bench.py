@@ -46,7 +46,7 @@ def parse():
                     help="served_mix: resident tensors per kind (SSYMV, 3-D, 4-D)")
     ap.add_argument("--requests", type=int, default=1000,
                     help="served_mix: requests per Poisson run")
-    ap.add_argument("--step-work", type=int, default=1 << 25,
+    ap.add_argument("--step-work", type=int, default=1 << 26,
                     help="served_mix: stored entries per serving step")
     ap.add_argument("--loads", default="0.5,0.8,0.95",
                     help="served_mix: offered loads as fractions of saturation")
