@@ -48,6 +48,8 @@ def parse():
                     help="served_mix: requests per Poisson run")
     ap.add_argument("--step-work", type=int, default=1 << 26,
                     help="served_mix: stored entries per serving step")
+    ap.add_argument("--max-slots", type=int, default=32,
+                    help="served_mix: requests running at once")
     ap.add_argument("--loads", default="0.5,0.8,0.95",
                     help="served_mix: offered loads as fractions of saturation")
     ap.add_argument("--algo", default="auto", choices=["auto", "views", "atomic", "lds"],
@@ -383,7 +385,7 @@ def served_mix(a, torch, systec, synth, dev):
         return reqs
 
     budget = 200 << 30
-    srv = systec.Server(budget_bytes=budget, max_slots=32, step_work_nnz=a.step_work)
+    srv = systec.Server(budget_bytes=budget, max_slots=a.max_slots, step_work_nnz=a.step_work)
     ids = [srv.register(t) for t in served_t]
 
     def out_for(p, R):
@@ -438,7 +440,7 @@ def served_mix(a, torch, systec, synth, dev):
     result = {"metric": "served p50/p99 latency (us) and throughput, BF16 continuous batching "
                         "vs plain FP32 one request at a time",
               "workload": "served_mix", "n_gpus": 1, "data": "synthetic (device generators)",
-              "server": {"max_slots": 32, "step_work_nnz": a.step_work},
+              "server": {"max_slots": a.max_slots, "step_work_nnz": a.step_work},
               "pool": {"tensors": len(pool), "per_kind": K, "resident_bytes": resident,
                        "budget_bytes": budget, "effective_nnz_total": int(sum(eff)),
                        "generate_s": round(t_gen, 2), "prepare_s": round(t_prep, 2)},

@@ -371,7 +371,7 @@ int systec_tensor_create_csr(int64_t n, int64_t nnz, const int32_t* rowptr, cons
   int64_t full = 0;
   if (nnz > 0 && (rc = expand_csr_size(n, nnz, rowptr, col, &full, s))) return rc;
   Tensor* t = nullptr;
-  if ((rc = tensor_create_csr(n, nnz, rowptr, col, val, 16384, s, &t))) return rc;
+  if ((rc = tensor_create_csr(n, nnz, rowptr, col, val, kPanelRows, s, &t))) return rc;
   t->effective_nnz = full;
   *out = new systec_tensor{t};
   return SYSTEC_OK;

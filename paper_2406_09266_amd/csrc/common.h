@@ -169,9 +169,13 @@ struct ZeroArgs {
   float* ptr[kStepReqs];
   int64_t count[kStepReqs];
 };
-constexpr int kServeBlock = 512;       // SSYMV step kernel
+// Prepared SSYMV panels: 32,768 rows (128 KiB of FP32 row sums in LDS),
+// run by 1,024-thread workgroups (one per CU).
+constexpr int kPanelRows = 32768;
+constexpr int kPanelThreads = 1024;
+constexpr int kServeBlock = kPanelThreads;  // SSYMV step kernel
 constexpr int kServeMttkrpBlock = 256; // MTTKRP step kernel
-constexpr int kServeLds = 16384 * 4;   // bytes: the row sums of one panel
+constexpr int kServeLds = kPanelRows * 4;  // bytes: the row sums of one panel
 // Work queues of the step launches on one stream: queue k's counter is
 // next[k * kQueueStride] (separate cache lines).
 constexpr int kStepQueues = 8;
@@ -183,12 +187,15 @@ struct StepCounter {
 // admitted requests; runs on a stream before its step launches.
 int launch_serve_prologue(const ZeroArgs& z, StepCounter* ctr, int nsets, hipStream_t s);
 // Step kernel variants: kind 0 is SSYMV (one variant); kinds 3, 4, 5 are
-// MTTKRP of that order, variant = 4 * (input is BF16) + lane class (R <= 8,
-// 16, 32, 64).
-constexpr int kStepVariants = 8;
-inline int step_variant(int dtype, int64_t R) {
+// MTTKRP of that order, variant = 8 * (input is BF16) + 4 * (16-byte lanes:
+// R a multiple of 8 BF16 or 4 FP32 columns and the input 16-byte aligned) +
+// lane class (R <= 8, 16, 32, 64).
+constexpr int kStepVariants = 16;
+inline int step_variant(int dtype, int64_t R, const void* in) {
   const int lane_class = R <= 8 ? 0 : R <= 16 ? 1 : R <= 32 ? 2 : 3;
-  return (dtype == SYSTEC_BF16 ? 4 : 0) + lane_class;
+  const int vec = dtype == SYSTEC_BF16 ? 8 : 4;
+  const bool vec_lanes = R % vec == 0 && (reinterpret_cast<uintptr_t>(in) & 15) == 0;
+  return (dtype == SYSTEC_BF16 ? 8 : 0) + (vec_lanes ? 4 : 0) + lane_class;
 }
 // Runs a persistent step kernel over the items of one (kind, variant) with
 // at most `grid` workgroups, taking items from the counter set `ctr`.

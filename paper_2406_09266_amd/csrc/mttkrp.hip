@@ -87,6 +87,40 @@ __global__ __launch_bounds__(kBlock) void mttkrp_views_kernel(ViewSet vs,
   }
 }
 
+// The same launch with 16-byte lanes (mttkrp_device.h): one wave per range
+// of kTileVec entries of a view.
+constexpr int kTileVec = 1024;
+
+template <int N, typename BT, int Lg, int T>
+__device__ __forceinline__ void vec_block(const ViewSet& vs, int b, const BT* __restrict__ B,
+                                          int ldb, float* __restrict__ C, int ldc, int col0,
+                                          int ncols) {
+  const int64_t wave = static_cast<int64_t>(b - vs.block0[T]) * kWaves + threadIdx.x / kWave;
+  const int64_t e0 = wave * kTileVec;
+  if (e0 >= vs.nnz[T]) return;
+  const int e1 = static_cast<int>(min<int64_t>(vs.nnz[T], e0 + kTileVec));
+  mttkrp_view_range_vec<N, BT, Lg, T>(static_cast<int>(e0), e1, vs.idx[T], vs.val[T], B, ldb, C,
+                                      ldc, col0, ncols);
+}
+
+template <int N, typename BT, int Lg>
+__global__ __launch_bounds__(kBlock) void mttkrp_views_vec_kernel(ViewSet vs,
+                                                                const BT* __restrict__ B, int ldb,
+                                                                float* __restrict__ C, int ldc,
+                                                                int col0, int ncols) {
+  const int b = blockIdx.x;
+  if (b < vs.block0[1]) {
+    vec_block<N, BT, Lg, 0>(vs, b, B, ldb, C, ldc, col0, ncols);
+  } else if (b < vs.block0[2]) {
+    vec_block<N, BT, Lg, 1>(vs, b, B, ldb, C, ldc, col0, ncols);
+  } else if (N == 3 || b < vs.block0[3]) {
+    vec_block<N, BT, Lg, 2>(vs, b, B, ldb, C, ldc, col0, ncols);
+  } else if constexpr (N > 3) {
+    if (N == 4 || b < vs.block0[4]) vec_block<N, BT, Lg, 3>(vs, b, B, ldb, C, ldc, col0, ncols);
+    else if constexpr (N > 4) vec_block<N, BT, Lg, 4>(vs, b, B, ldb, C, ldc, col0, ncols);
+  }
+}
+
 template <int N, typename BT, int L, bool kSym>
 void launch_one(int nnz, const IdxPtrs& ip, const float* val, const BT* B, int ldb, float* C,
                 int ldc, int col0, int ncols, hipStream_t s) {
@@ -161,7 +195,7 @@ void launch_views_cols(const ViewSet& vs, const BT* B, int ldb, float* C, int ld
 }
 
 template <int N, typename BT>
-void launch_views_typed(const Tensor* tn, const BT* B, int R, float* C, hipStream_t s) {
+ViewSet view_set(const Tensor* tn, int tile) {
   ViewSet vs{};
   int64_t blocks = 0;
   for (int t = 0; t < N; ++t) {
@@ -169,11 +203,46 @@ void launch_views_typed(const Tensor* tn, const BT* B, int R, float* C, hipStrea
     vs.val[t] = tn->vval[t];
     vs.nnz[t] = static_cast<int>(tn->vnnz[t]);
     vs.block0[t] = static_cast<int>(blocks);
-    const int64_t tiles = (tn->vnnz[t] + kTileE - 1) / kTileE;
+    const int64_t tiles = (tn->vnnz[t] + tile - 1) / tile;
     blocks += (tiles + kWaves - 1) / kWaves;
   }
   for (int t = N; t <= 5; ++t) vs.block0[t] = static_cast<int>(blocks);
-  if (blocks == 0) return;
+  return vs;
+}
+
+template <int N, typename BT, int Lg>
+void launch_vec_cols(const ViewSet& vs, const BT* B, int R, float* C, int col0, int ncols,
+                     hipStream_t s) {
+  mttkrp_views_vec_kernel<N, BT, Lg>
+      <<<dim3(vs.block0[N]), dim3(kBlock), 0, s>>>(vs, B, R, C, R, col0, ncols);
+}
+
+// 16-byte lanes when rows are 16-byte aligned (R a multiple of the vector
+// and B 16-byte aligned), else one lane per column.
+template <int N, typename BT>
+void launch_views_typed(const Tensor* tn, const BT* B, int R, float* C, hipStream_t s) {
+  constexpr int V = vec_cols<BT>();
+  if (R % V == 0 && (reinterpret_cast<uintptr_t>(B) & 15) == 0) {
+    const ViewSet vs = view_set<N, BT>(tn, kTileVec);
+    if (vs.block0[N] == 0) return;
+    for (int c0 = 0; c0 < R; c0 += 64) {
+      const int w = std::min(64, R - c0);  // a multiple of V
+      int lanes = 1;
+      while (lanes * V < w) lanes *= 2;
+      switch (lanes) {
+        case 1: launch_vec_cols<N, BT, 1>(vs, B, R, C, c0, w, s); break;
+        case 2: launch_vec_cols<N, BT, 2>(vs, B, R, C, c0, w, s); break;
+        case 4: launch_vec_cols<N, BT, 4>(vs, B, R, C, c0, w, s); break;
+        case 8: launch_vec_cols<N, BT, 8>(vs, B, R, C, c0, w, s); break;
+        default:
+          if constexpr (V == 4) launch_vec_cols<N, BT, 16>(vs, B, R, C, c0, w, s);
+          break;
+      }
+    }
+    return;
+  }
+  const ViewSet vs = view_set<N, BT>(tn, kTileE);
+  if (vs.block0[N] == 0) return;
   if (R <= 8) launch_views_cols<N, BT, 8>(vs, B, R, C, R, 0, R, s);
   else if (R <= 16) launch_views_cols<N, BT, 16>(vs, B, R, C, R, 0, R, s);
   else if (R <= 32) launch_views_cols<N, BT, 32>(vs, B, R, C, R, 0, R, s);

@@ -204,5 +204,189 @@ __device__ __forceinline__ void mttkrp_view_tile_slot(int t, int e0, int e1, con
   }
 }
 
+// ---- 16-byte lanes ----------------------------------------------------------
+// The view kernels above give every output column its own lane, so a lane
+// loads 2 (BF16) or 4 (FP32) bytes of a factor row and a wave instruction
+// covers only 64/L rows: at R = 32 the kernels issue a load instruction for
+// every two rows, and their time goes to issuing loads, not to moving bytes.
+// Here each lane loads 16 bytes of a row (V = 8 BF16 or 4 FP32 columns), so a
+// group of Lg = R/V lanes covers a row and a wave instruction covers 64/Lg
+// rows. Requires R to be a multiple of V (rows stay 16-byte aligned).
+
+// entries in flight per lane group (a group already covers a whole row)
+constexpr int kUnrollVec = 2;
+
+template <typename BT>
+constexpr int vec_cols() {
+  return 16 / static_cast<int>(sizeof(BT));
+}
+
+template <typename BT>
+__device__ __forceinline__ void unpack_vec(const uint4& u, float (&out)[vec_cols<BT>()]) {
+  if constexpr (sizeof(BT) == 2) {
+    const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      out[2 * q] = __uint_as_float(w[q] << 16);              // element 2q (low half)
+      out[2 * q + 1] = __uint_as_float(w[q] & 0xffff0000u);  // element 2q+1 (high half)
+    }
+  } else {
+    out[0] = __uint_as_float(u.x);
+    out[1] = __uint_as_float(u.y);
+    out[2] = __uint_as_float(u.z);
+    out[3] = __uint_as_float(u.w);
+  }
+}
+
+// Sum over the lanes that hold the same columns (lanes equal modulo Lg).
+template <int Lg>
+__device__ __forceinline__ float lane_group_sum(float v) {
+#pragma unroll
+  for (int d = Lg; d < kWave; d *= 2) v += __shfl_xor(v, d);
+  return v;
+}
+
+// Writes the wave's sum for output row `row` with one atomic per column: the
+// sums of group 0 (lane sub holds columns sub*V .. sub*V+V-1) are spread so
+// that lane l adds column l, and consecutive lanes hit consecutive addresses.
+template <int V, int Lg>
+__device__ __forceinline__ void emit_row_spread(float* __restrict__ C, int ldc, int row, int col0,
+                                                int ncols, const float (&acc)[V]) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int src = lane / V, j = lane - src * V;
+  float x = 0.0f;
+#pragma unroll
+  for (int q = 0; q < V; ++q) {
+    const float t = __shfl(acc[q], src);
+    x = (j == q) ? t : x;
+  }
+  if (lane < ncols && lane < V * Lg)
+    atomic_add_noret(C + static_cast<int64_t>(row) * ldc + col0 + lane, x);
+}
+
+// A wave runs entries [e0, e1) of view T (sorted by c_T). Lane group g takes
+// entry base + u*G + g of each iteration, so index loads are coalesced. Each
+// lane sums the entries of the wave's current output row `cur`; when an
+// iteration reaches a later row, the sums for `cur` are added across the
+// groups and written once, the entries of the iteration's last row start the
+// next sum, and rows strictly between (runs shorter than an iteration) are
+// written lane by lane.
+template <int N, typename BT, int Lg, int T>
+__device__ __forceinline__ void mttkrp_view_range_vec(int e0, int e1, const IdxPtrs& ip,
+                                                      const float* __restrict__ val,
+                                                      const BT* __restrict__ B, int ldb,
+                                                      float* __restrict__ C, int ldc, int col0,
+                                                      int ncols) {
+  constexpr int V = vec_cols<BT>();
+  constexpr int G = kWave / Lg;
+  if (e0 >= e1) return;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int g = lane / Lg, sub = lane - g * Lg;
+  const bool lane_cols = sub * V < ncols;
+  const int col = col0 + sub * V;
+  const int32_t* __restrict__ out_idx = ip.p[T];
+  int cur = out_idx[e0];  // same address in every lane
+  float acc[V], nxt[V];
+#pragma unroll
+  for (int j = 0; j < V; ++j) acc[j] = nxt[j] = 0.0f;
+  for (int base = e0; base < e1; base += G * kUnrollVec) {
+    int c[kUnrollVec][N];
+    float v[kUnrollVec];
+    bool ok[kUnrollVec];
+#pragma unroll
+    for (int u = 0; u < kUnrollVec; ++u) {
+      const int e = base + u * G + g;
+      ok[u] = e < e1;
+#pragma unroll
+      for (int s = 0; s < N; ++s) c[u][s] = ok[u] ? ip.p[s][e] : 0;
+      v[u] = ok[u] ? val[e] : 0.0f;
+    }
+    uint4 raw[kUnrollVec][N];
+#pragma unroll
+    for (int u = 0; u < kUnrollVec; ++u)
+#pragma unroll
+      for (int s = 0; s < N; ++s) {
+        if (s == T) continue;
+        raw[u][s] = (ok[u] && lane_cols)
+                        ? *reinterpret_cast<const uint4*>(B + static_cast<int64_t>(c[u][s]) * ldb + col)
+                        : make_uint4(0u, 0u, 0u, 0u);
+      }
+    const int last = out_idx[min(e1, base + G * kUnrollVec) - 1];  // uniform
+    float p[kUnrollVec][V];
+#pragma unroll
+    for (int u = 0; u < kUnrollVec; ++u) {
+      const float kv = ok[u] ? coef_table<N>().coef[equality_mask_of(c[u], N)][T] * v[u] : 0.0f;
+#pragma unroll
+      for (int j = 0; j < V; ++j) p[u][j] = kv;
+#pragma unroll
+      for (int s = 0; s < N; ++s) {
+        if (s == T) continue;
+        float b[V];
+        unpack_vec<BT>(raw[u][s], b);
+#pragma unroll
+        for (int j = 0; j < V; ++j) p[u][j] *= b[j];
+      }
+    }
+    if (last == cur) {  // the whole iteration continues the current run
+#pragma unroll
+      for (int u = 0; u < kUnrollVec; ++u)
+#pragma unroll
+        for (int j = 0; j < V; ++j) acc[j] += p[u][j];
+      continue;
+    }
+#pragma unroll
+    for (int u = 0; u < kUnrollVec; ++u) {
+      if (!ok[u]) continue;
+      const int row = c[u][T];
+      if (row == cur) {
+#pragma unroll
+        for (int j = 0; j < V; ++j) acc[j] += p[u][j];
+      } else if (row == last) {
+#pragma unroll
+        for (int j = 0; j < V; ++j) nxt[j] += p[u][j];
+      } else if (lane_cols) {  // a run shorter than an iteration
+        float* out = C + static_cast<int64_t>(row) * ldc + col;
+#pragma unroll
+        for (int j = 0; j < V; ++j) atomic_add_noret(out + j, p[u][j]);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < V; ++j) acc[j] = lane_group_sum<Lg>(acc[j]);
+    emit_row_spread<V, Lg>(C, ldc, cur, col0, ncols, acc);
+    cur = last;
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      acc[j] = nxt[j];
+      nxt[j] = 0.0f;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < V; ++j) acc[j] = lane_group_sum<Lg>(acc[j]);
+  emit_row_spread<V, Lg>(C, ldc, cur, col0, ncols, acc);
+}
+
+// Runs view slot t (a value uniform across the wave) with 16-byte lanes.
+template <int N, typename BT, int Lg>
+__device__ __forceinline__ void mttkrp_view_range_vec_slot(int t, int e0, int e1,
+                                                           const IdxPtrs& idx,
+                                                           const float* __restrict__ val,
+                                                           const BT* __restrict__ B, int ldb,
+                                                           float* __restrict__ C, int ldc,
+                                                           int col0, int ncols) {
+  switch (t) {
+    case 0: mttkrp_view_range_vec<N, BT, Lg, 0>(e0, e1, idx, val, B, ldb, C, ldc, col0, ncols); break;
+    case 1: mttkrp_view_range_vec<N, BT, Lg, 1>(e0, e1, idx, val, B, ldb, C, ldc, col0, ncols); break;
+    case 2: mttkrp_view_range_vec<N, BT, Lg, 2>(e0, e1, idx, val, B, ldb, C, ldc, col0, ncols); break;
+    case 3:
+      if constexpr (N > 3)
+        mttkrp_view_range_vec<N, BT, Lg, 3>(e0, e1, idx, val, B, ldb, C, ldc, col0, ncols);
+      break;
+    default:
+      if constexpr (N > 4)
+        mttkrp_view_range_vec<N, BT, Lg, 4>(e0, e1, idx, val, B, ldb, C, ldc, col0, ncols);
+      break;
+  }
+}
+
 }  // namespace dev
 }  // namespace systec

@@ -68,7 +68,24 @@ __device__ __forceinline__ int find_req(const StepArgs& a, int i) {
 }
 
 // One MTTKRP item is a range of a few tiles of one view; the waves of the
-// workgroup take every fourth tile.
+// workgroup take every fourth tile (one lane per column) or a quarter of the
+// range each (16-byte lanes, which sum runs across the wave).
+template <int N, typename BT, int L>
+__device__ __forceinline__ void view_range_vec(const ServeTensor* t, const ServeUnit& u,
+                                               const StepReq& q) {
+  constexpr int V = vec_cols<BT>();
+  constexpr int Lg = (L / V) < 1 ? 1 : (L / V);  // lanes per row at R <= L
+  IdxPtrs ip{};
+#pragma unroll
+  for (int s = 0; s < N; ++s) ip.p[s] = uni_ptr(static_cast<const int32_t*>(t->p[u.a][s]));
+  const float* val = uni_ptr(t->val[u.a]);
+  const BT* B = static_cast<const BT*>(q.in);
+  const int w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  const int per = (u.c - u.b + nw - 1) / nw;
+  const int e0 = min(u.c, u.b + w * per), e1 = min(u.c, e0 + per);
+  mttkrp_view_range_vec_slot<N, BT, Lg>(u.a, e0, e1, ip, val, B, q.R, q.out, q.R, 0, q.R);
+}
+
 template <int N, typename BT, int L>
 __device__ __forceinline__ void view_range(const ServeTensor* t, const ServeUnit& u,
                                            const StepReq& q) {
@@ -110,7 +127,7 @@ __device__ __forceinline__ int take_item(StepCounter* c, int n, int* q, int* s_i
   return i;
 }
 
-// SSYMV items need the panel's row sums in LDS (512 threads, 64 KiB); MTTKRP
+// SSYMV items need the panel's row sums in LDS (1,024 threads, 128 KiB); MTTKRP
 // items need no LDS and run at full occupancy (256 threads, one kernel per
 // tensor order so that each keeps the registers of its own order); the four
 // waves of an MTTKRP workgroup share an item of a few tiles each.
@@ -136,9 +153,9 @@ __global__ __launch_bounds__(kServeBlock) void serve_ssymv_kernel(StepArgs a, St
   }
 }
 
-// One MTTKRP step kernel per (order, factor dtype, lane group width), so that
-// each keeps only the registers of its own variant.
-template <int N, typename BT, int L>
+// One MTTKRP step kernel per (order, input dtype, lane layout, lane class),
+// so that each keeps only the registers of its own variant.
+template <int N, typename BT, int L, bool kVec>
 __global__ __launch_bounds__(kServeMttkrpBlock) void serve_mttkrp_kernel(StepArgs a,
                                                                          StepCounter* ctr) {
   __shared__ int s_item;
@@ -148,50 +165,39 @@ __global__ __launch_bounds__(kServeMttkrpBlock) void serve_mttkrp_kernel(StepArg
     const StepReq& r = a.req[find_req(a, i)];
     const ServeTensor* t = r.t;
     const ServeUnit u = load_unit(t, r.unit0 + (i - r.item0));
-    view_range<N, BT, L>(t, u, r);
+    if constexpr (kVec) view_range_vec<N, BT, L>(t, u, r);
+    else view_range<N, BT, L>(t, u, r);
   }
 }
 
-// The kernel of a (kind, variant) pair: kind 0 is SSYMV; kinds 3, 4, 5 are
-// MTTKRP of that order with variant = 4 * (dtype is BF16) + lane class
-// (L = 8, 16, 32, 64).
+template <int N, typename BT, bool kVec>
+const void* mttkrp_kernel_lanes(int lane_class) {
+  switch (lane_class) {
+    case 0: return reinterpret_cast<const void*>(serve_mttkrp_kernel<N, BT, 8, kVec>);
+    case 1: return reinterpret_cast<const void*>(serve_mttkrp_kernel<N, BT, 16, kVec>);
+    case 2: return reinterpret_cast<const void*>(serve_mttkrp_kernel<N, BT, 32, kVec>);
+    default: return reinterpret_cast<const void*>(serve_mttkrp_kernel<N, BT, 64, kVec>);
+  }
+}
+
+// The kernel of an MTTKRP variant (see step_variant).
 template <int N>
 const void* mttkrp_kernel_of(int variant) {
-  const bool bf16 = variant >= 4;
-  switch (variant & 3) {
-    case 0: return bf16 ? reinterpret_cast<const void*>(serve_mttkrp_kernel<N, uint16_t, 8>)
-                        : reinterpret_cast<const void*>(serve_mttkrp_kernel<N, float, 8>);
-    case 1: return bf16 ? reinterpret_cast<const void*>(serve_mttkrp_kernel<N, uint16_t, 16>)
-                        : reinterpret_cast<const void*>(serve_mttkrp_kernel<N, float, 16>);
-    case 2: return bf16 ? reinterpret_cast<const void*>(serve_mttkrp_kernel<N, uint16_t, 32>)
-                        : reinterpret_cast<const void*>(serve_mttkrp_kernel<N, float, 32>);
-    default: return bf16 ? reinterpret_cast<const void*>(serve_mttkrp_kernel<N, uint16_t, 64>)
-                         : reinterpret_cast<const void*>(serve_mttkrp_kernel<N, float, 64>);
-  }
+  const int lane_class = variant & 3;
+  const bool vec = (variant & 4) != 0;
+  if (variant & 8)
+    return vec ? mttkrp_kernel_lanes<N, uint16_t, true>(lane_class)
+               : mttkrp_kernel_lanes<N, uint16_t, false>(lane_class);
+  return vec ? mttkrp_kernel_lanes<N, float, true>(lane_class)
+             : mttkrp_kernel_lanes<N, float, false>(lane_class);
 }
 
 template <int N>
-void launch_mttkrp_variant(int variant, const StepArgs& a, dim3 g, StepCounter* ctr, hipStream_t s) {
-  const bool bf16 = variant >= 4;
-  const dim3 b(kServeMttkrpBlock);
-  switch (variant & 3) {
-    case 0:
-      if (bf16) serve_mttkrp_kernel<N, uint16_t, 8><<<g, b, 0, s>>>(a, ctr);
-      else serve_mttkrp_kernel<N, float, 8><<<g, b, 0, s>>>(a, ctr);
-      break;
-    case 1:
-      if (bf16) serve_mttkrp_kernel<N, uint16_t, 16><<<g, b, 0, s>>>(a, ctr);
-      else serve_mttkrp_kernel<N, float, 16><<<g, b, 0, s>>>(a, ctr);
-      break;
-    case 2:
-      if (bf16) serve_mttkrp_kernel<N, uint16_t, 32><<<g, b, 0, s>>>(a, ctr);
-      else serve_mttkrp_kernel<N, float, 32><<<g, b, 0, s>>>(a, ctr);
-      break;
-    default:
-      if (bf16) serve_mttkrp_kernel<N, uint16_t, 64><<<g, b, 0, s>>>(a, ctr);
-      else serve_mttkrp_kernel<N, float, 64><<<g, b, 0, s>>>(a, ctr);
-      break;
-  }
+hipError_t launch_mttkrp_variant(int variant, const StepArgs& a, dim3 g, StepCounter* ctr,
+                                 hipStream_t s) {
+  const void* k = mttkrp_kernel_of<N>(variant);
+  void* args[] = {const_cast<StepArgs*>(&a), &ctr};
+  return hipLaunchKernel(k, g, dim3(kServeMttkrpBlock), args, 0, s);
 }
 
 }  // namespace
@@ -208,20 +214,26 @@ int launch_serve_step(int kind, int variant, const StepArgs& a, int grid, StepCo
                       hipStream_t s) {
   if (a.nitems == 0) return SYSTEC_OK;
   const dim3 g(std::max(1, std::min(grid, a.nitems)));
+  hipError_t e = hipSuccess;
   switch (kind) {
-    case 0: serve_ssymv_kernel<<<g, dim3(kServeBlock), kServeLds, s>>>(a, ctr); break;
-    case 3: launch_mttkrp_variant<3>(variant, a, g, ctr, s); break;
-    case 4: launch_mttkrp_variant<4>(variant, a, g, ctr, s); break;
-    default: launch_mttkrp_variant<5>(variant, a, g, ctr, s); break;
+    case 0: serve_ssymv_kernel<<<g, dim3(kServeBlock), kServeLds, s>>>(a, ctr); break;  // LDS limit set by serve_blocks_per_cu
+    case 3: e = launch_mttkrp_variant<3>(variant, a, g, ctr, s); break;
+    case 4: e = launch_mttkrp_variant<4>(variant, a, g, ctr, s); break;
+    default: e = launch_mttkrp_variant<5>(variant, a, g, ctr, s); break;
   }
+  if (e != hipSuccess) return check_hip(e, "serve mttkrp kernel launch");
   return check_launch(kind == 0 ? "serve ssymv kernel" : "serve mttkrp kernel");
 }
 
 int serve_blocks_per_cu(int kind, int variant, int* blocks) {
   hipError_t e;
   if (kind == 0) {
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, serve_ssymv_kernel, kServeBlock,
-                                                     kServeLds);
+    // more than the default 64 KiB of dynamic LDS (set once, before any launch)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(serve_ssymv_kernel),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kServeLds);
+    if (e == hipSuccess)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, serve_ssymv_kernel, kServeBlock,
+                                                       kServeLds);
   } else {
     const void* k = kind == 3 ? mttkrp_kernel_of<3>(variant)
                     : kind == 4 ? mttkrp_kernel_of<4>(variant)

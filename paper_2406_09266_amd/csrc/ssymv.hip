@@ -235,7 +235,7 @@ __global__ __launch_bounds__(1024) void reduce_partials_f64(const float* __restr
 }
 
 template <typename XT>
-__global__ __launch_bounds__(512) void ssymv_panel_kernel(
+__global__ __launch_bounds__(kPanelThreads) void ssymv_panel_kernel(
     int n, int H, const int32_t* __restrict__ chunk_panel,
     const int32_t* __restrict__ chunk_tile_begin, const int32_t* __restrict__ chunk_tile_end,
     const int32_t* __restrict__ pcol, const uint16_t* __restrict__ prow,
@@ -322,13 +322,24 @@ int launch_ssymv_panel(const Tensor* t, const void* x, systec_dtype xdt, float* 
   if (rc != SYSTEC_OK || t->nchunks == 0) return rc;
   const size_t lds = static_cast<size_t>(t->panel_rows) * sizeof(float);
   const int n = static_cast<int>(t->dim);
+  // more than the default 64 KiB of dynamic LDS
+  rc = check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(ssymv_panel_kernel<float>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     static_cast<int>(lds)),
+                 "hipFuncSetAttribute(dynamic LDS)");
+  if (!rc)
+    rc = check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(ssymv_panel_kernel<uint16_t>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       static_cast<int>(lds)),
+                   "hipFuncSetAttribute(dynamic LDS)");
+  if (rc) return rc;
   LaunchTimer timer(s);
   if (xdt == SYSTEC_F32)
-    ssymv_panel_kernel<float><<<dim3(t->nchunks), dim3(512), lds, s>>>(
+    ssymv_panel_kernel<float><<<dim3(t->nchunks), dim3(kPanelThreads), lds, s>>>(
         n, t->panel_rows, t->chunk_panel, t->chunk_tile_begin, t->chunk_tile_end, t->pcol,
         t->prow, t->pval, static_cast<const float*>(x), y);
   else
-    ssymv_panel_kernel<uint16_t><<<dim3(t->nchunks), dim3(512), lds, s>>>(
+    ssymv_panel_kernel<uint16_t><<<dim3(t->nchunks), dim3(kPanelThreads), lds, s>>>(
         n, t->panel_rows, t->chunk_panel, t->chunk_tile_begin, t->chunk_tile_end, t->pcol,
         t->prow, t->pval, static_cast<const uint16_t*>(x), y);
   return check_launch("ssymv panel kernel");

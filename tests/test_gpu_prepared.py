@@ -60,7 +60,7 @@ def test_prepared_ssymv(case, xdtype):
 def test_prepared_ssymv_empty_rows_and_panels():
     import torch
     # rows only in the last panel; earlier panels empty
-    n = 50000
+    n = 140000
     rowptr = np.zeros(n + 1, dtype=np.int32)
     rowptr[n - 100:] = np.arange(0, 101, dtype=np.int32)  # rows n-100.. hold one entry each
     cols = np.arange(n - 100, n, dtype=np.int32)           # on the diagonal
@@ -109,6 +109,27 @@ def test_prepared_mttkrp(order, dim, nnz, R, bdtype, algo):
     want, counts = oracle.mttkrp(order, dim, t["idx"].T, f32(t["val"]), Bref)
     assert rel_err(C, want) <= TOL32
     assert T.effective_nnz == counts["effective_nnz"]
+    T.close()
+
+
+@pytest.mark.parametrize("order,dim,nnz", [(3, 400, 30011), (4, 150, 20021), (5, 70, 12007)])
+@pytest.mark.parametrize("R,bdtype", [(8, "bf16"), (24, "bf16"), (64, "bf16"), (72, "bf16"),
+                                      (136, "bf16"), (4, "f32"), (12, "f32"), (64, "f32")])
+def test_prepared_mttkrp_vector_lanes(order, dim, nnz, R, bdtype):
+    """Slot views with 16-byte lanes (R a multiple of 8 BF16 or 4 FP32
+    columns): one to sixteen lanes per row, idle lanes when R is not a power
+    of two, and 64-column blocks with a ragged last block."""
+    t = synth.sym_coo(order, dim, nnz, repeat_frac=0.2, seed=3000 + order * 13 + R)
+    B = synth.dense_uniform((dim, R), seed=R + 7)
+    T = systec.Tensor.from_coo([dev(a) for a in t["idx"]], dev(t["val"].astype(np.float32)), dim)
+    Bd = dev(B.astype(np.float32))
+    Bref = f32(B)
+    if bdtype == "bf16":
+        Bd = systec.quantize_bf16(Bd)
+        Bref = oracle.round_bf16(B.astype(np.float32))
+    C = T.mttkrp(Bd, algo="views").cpu().numpy()
+    want, _ = oracle.mttkrp(order, dim, t["idx"].T, f32(t["val"]), Bref)
+    assert rel_err(C, want) <= TOL32
     T.close()
 
 
