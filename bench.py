@@ -46,7 +46,7 @@ def parse():
                     help="served_mix: resident tensors per kind (SSYMV, 3-D, 4-D)")
     ap.add_argument("--requests", type=int, default=1000,
                     help="served_mix: requests per Poisson run")
-    ap.add_argument("--step-work", type=int, default=1 << 26,
+    ap.add_argument("--step-work", type=int, default=1 << 27,
                     help="served_mix: stored entries per serving step")
     ap.add_argument("--max-slots", type=int, default=32,
                     help="served_mix: requests running at once")

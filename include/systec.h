@@ -321,7 +321,9 @@ typedef struct systec_server systec_server;
 typedef struct {
   uint64_t budget_bytes;  /* resident tensors + in-flight request buffers */
   int32_t max_slots;      /* requests running at once */
-  int64_t step_work_nnz;  /* work per step, in stored entries */
+  int64_t step_work_nnz;  /* work per step, in stored entries: larger steps raise
+                             throughput, smaller steps lower the latency of small
+                             requests sharing steps with large ones */
   int32_t device;         /* HIP device ordinal */
   int32_t max_queue;      /* waiting requests before SYSTEC_EBUSY (<= 0: 2^20) */
 } systec_serve_config;
