@@ -243,6 +243,19 @@ class GpuExecutor {
     return serve::kOk;
   }
 
+  // The stream (kernel kind) that runs an operand's work.
+  int part_of(const serve::TensorEntry& t) const { return t.kind == 0 ? 0 : t.order - 2; }
+
+  int query_part(int64_t step_id, int part, std::string* err) {
+    const hipError_t e = hipEventQuery(ev_[step_id % kRing][part]);
+    if (e == hipErrorNotReady) return 0;
+    if (e != hipSuccess) {
+      *err = std::string("serving step failed: ") + hipGetErrorString(e);
+      return -1;
+    }
+    return 1;
+  }
+
   int query(int64_t step_id, std::string* err) {
     const int slot = static_cast<int>(step_id % kRing);
     for (hipEvent_t ev : ev_[slot]) {

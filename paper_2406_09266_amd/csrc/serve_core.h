@@ -10,11 +10,18 @@
 // is free and the budget allows; a request that could never fit returns
 // SYSTEC_EBUDGET at submit. Each step takes work units (chunks of the
 // prepared operand) from the admitted requests, up to a work budget in
-// entries (half shared round-robin, half in admission order), and hands them
-// to the executor as one launch; requests admitted while a step runs join the
-// next one (continuous batching). A
-// request retires when the step holding its last unit has completed; its
-// latency runs from its arrival to that moment, queueing included.
+// entries (every running request gets at least one unit, then half of the
+// budget is shared round-robin and the rest goes in admission order), and
+// hands them to the executor as one launch; requests admitted while a step
+// runs join the next one (continuous batching). The executor runs a step in
+// parts (the GPU executor: one stream per kernel kind), each in order across
+// steps; a request retires as soon as the part that runs its work has
+// completed the step holding its last unit, and its latency runs from its
+// arrival to that moment, queueing included.
+//
+// Executor interface: request_bytes(tensor, dtype, R), part_of(tensor) in
+// [0, 8), launch(plan, err), query(step, err) and query_part(step, part, err)
+// (1 done, 0 running, -1 failed), release(tensor).
 #pragma once
 
 #include <algorithm>
@@ -89,6 +96,7 @@ struct Request {
   int64_t arrival_ns = 0, admit_ns = 0, done_ns = 0;
   size_t next_unit = 0;
   int64_t last_step = -1;
+  int part = 0;  // the executor part (stream) that runs this request's work
   std::string error;
 };
 
@@ -299,6 +307,8 @@ class Scheduler {
     return std::chrono::system_clock::now() + d;
   }
 
+  static constexpr int kParts = 8;  // executor parts (Exec::part_of returns 0..7)
+
   struct InFlight {
     int64_t step_id;
     std::vector<std::shared_ptr<Request>> reqs;  // every request with an item in the step
@@ -315,6 +325,7 @@ class Scheduler {
       auto& r = queue_.front();
       if (bytes_in_use_ + r->bytes > cfg_.budget_bytes) break;  // FIFO: the head waits
       bytes_in_use_ += r->bytes;
+      r->part = exec_.part_of(*r->tensor);
       r->state = kRunning;
       r->admit_ns = now_ns();
       plan.zero.push_back(r.get());
@@ -373,27 +384,57 @@ class Scheduler {
       }
   }
 
+  void retire_one_locked(const std::shared_ptr<Request>& r, bool ok, const std::string& err,
+                         int64_t t) {
+    if (!ok) {
+      r->state = kFailed;
+      r->error = err;
+      ++failed_;
+    } else {
+      r->state = kDone;
+      r->done_ns = t;
+      latencies_us_.push_back((t - r->arrival_ns) * 1e-3);
+      done_eff_nnz_ += r->tensor->effective_nnz;
+      last_done_ns_ = std::max(last_done_ns_, t);
+    }
+    bytes_in_use_ -= r->bytes;
+    r->tensor.reset();  // drop the reference: the request no longer pins the tensor
+    active_.erase(std::remove(active_.begin(), active_.end(), r), active_.end());
+  }
+
   void retire_locked(const InFlight& f, bool ok, const std::string& err) {
     const int64_t t = now_ns();
     for (auto& r : f.reqs) {
       if (r->state != kRunning) continue;
-      if (!ok) {
-        r->state = kFailed;
-        r->error = err;
-        ++failed_;
-      } else if (r->last_step == f.step_id) {
-        r->state = kDone;
-        r->done_ns = t;
-        latencies_us_.push_back((t - r->arrival_ns) * 1e-3);
-        done_eff_nnz_ += r->tensor->effective_nnz;
-        last_done_ns_ = std::max(last_done_ns_, t);
-      } else {
-        continue;
-      }
-      bytes_in_use_ -= r->bytes;
-      r->tensor.reset();  // drop the reference: the request no longer pins the tensor
-      active_.erase(std::remove(active_.begin(), active_.end(), r), active_.end());
+      if (ok && r->last_step != f.step_id) continue;
+      retire_one_locked(r, ok, err, t);
     }
+  }
+
+  // Retires the requests whose last step has completed on their own part of
+  // the executor (a request does not wait for the other parts' work of its
+  // step, nor for earlier steps of other parts). Returns whether any retired.
+  bool retire_parts_locked(std::unique_lock<std::mutex>& lk) {
+    bool retired = false;
+    for (auto& f : inflight_) {
+      int state[kParts];
+      std::string errs[kParts];
+      std::fill(state, state + kParts, -2);  // not queried yet
+      for (auto& r : f.reqs) {
+        if (r->state != kRunning || r->last_step != f.step_id) continue;
+        const int part = r->part;
+        if (state[part] == -2) {
+          lk.unlock();
+          state[part] = exec_.query_part(f.step_id, part, &errs[part]);
+          lk.lock();
+        }
+        if (state[part] != 0) {
+          retire_one_locked(r, state[part] > 0, errs[part], now_ns());
+          retired = true;
+        }
+      }
+    }
+    return retired;
   }
 
   void loop() {
@@ -431,8 +472,8 @@ class Scheduler {
           continue;
         }
       }
-      // 2. retire completed steps, in order
-      bool retired = false;
+      // 2. retire requests done on their own part, then completed steps in order
+      bool retired = retire_parts_locked(lk);
       while (!inflight_.empty()) {
         std::string err;
         lk.unlock();

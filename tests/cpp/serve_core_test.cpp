@@ -75,6 +75,8 @@ struct FakeExec {
     }
     return 1;
   }
+  int part_of(const TensorEntry& t) const { return t.kind; }
+  int query_part(int64_t step, int, std::string* err) { return query(step, err); }
   void finished(int64_t req) {
     std::lock_guard<std::mutex> lk(mu);
     running_bytes.erase(req);
