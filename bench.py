@@ -50,6 +50,11 @@ def parse():
                     help="served_mix: stored entries per serving step")
     ap.add_argument("--max-slots", type=int, default=32,
                     help="served_mix: requests running at once")
+    ap.add_argument("--max-inflight", type=int, default=0,
+                    help="served_mix: steps queued on the device at once (0: the server default)")
+    ap.add_argument("--streams", type=int, default=0,
+                    help="served_mix: 1 runs a step's kernel kinds in order on one stream, "
+                         "0 one stream per kind")
     ap.add_argument("--loads", default="0.5,0.8,0.95",
                     help="served_mix: offered loads as fractions of saturation")
     ap.add_argument("--algo", default="auto", choices=["auto", "views", "atomic", "lds"],
@@ -385,7 +390,8 @@ def served_mix(a, torch, systec, synth, dev):
         return reqs
 
     budget = 200 << 30
-    srv = systec.Server(budget_bytes=budget, max_slots=a.max_slots, step_work_nnz=a.step_work)
+    srv = systec.Server(budget_bytes=budget, max_slots=a.max_slots, step_work_nnz=a.step_work,
+                        max_inflight=a.max_inflight, streams=a.streams)
     ids = [srv.register(t) for t in served_t]
 
     def out_for(p, R):
@@ -430,6 +436,21 @@ def served_mix(a, torch, systec, synth, dev):
         return {"p50_us": pct(50), "p99_us": pct(99), "req_per_s": len(lat) / span,
                 "eff_nnz_per_s": eff_done / span}
 
+    def run_plain_async(reqs):
+        """The plain kernels back to back with no synchronization between
+        requests: the device-bound rate of the one-at-a-time form."""
+        outs = [out_for(p, R) for p, R in reqs]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for (p, R), o in zip(reqs, outs):
+            x = inputs[(p, R)][0]
+            if kinds[p] == "ssymv":
+                plain_t[p].ssymv(x, out=o)
+            else:
+                plain_t[p].mttkrp(x, out=o)
+        torch.cuda.synchronize()
+        return len(reqs) / (time.perf_counter() - t0)
+
     # warm-up, then saturation (everything arrives at once)
     run_served(draw(64, 1), [0.0] * 64)
     n_sat = max(200, a.requests // 3)
@@ -437,16 +458,19 @@ def served_mix(a, torch, systec, synth, dev):
     st = run_served(sat_reqs, [0.0] * n_sat)
     sat = st["req_per_s"]
     plain_sat = run_plain(sat_reqs, [0.0] * n_sat)
+    plain_async = run_plain_async(sat_reqs)
     result = {"metric": "served p50/p99 latency (us) and throughput, BF16 continuous batching "
                         "vs plain FP32 one request at a time",
               "workload": "served_mix", "n_gpus": 1, "data": "synthetic (device generators)",
-              "server": {"max_slots": a.max_slots, "step_work_nnz": a.step_work},
+              "server": {"max_slots": a.max_slots, "step_work_nnz": a.step_work,
+                         "max_inflight": a.max_inflight or 2, "streams": a.streams},
               "pool": {"tensors": len(pool), "per_kind": K, "resident_bytes": resident,
                        "budget_bytes": budget, "effective_nnz_total": int(sum(eff)),
                        "generate_s": round(t_gen, 2), "prepare_s": round(t_prep, 2)},
               "saturation": {"served_req_per_s": sat, "served_eff_nnz_per_s": st["eff_nnz_per_s"],
                              "plain_req_per_s": plain_sat["req_per_s"],
                              "plain_eff_nnz_per_s": plain_sat["eff_nnz_per_s"],
+                             "plain_back_to_back_req_per_s": plain_async,
                              "requests": n_sat},
               "loads": []}
     for frac in [float(v) for v in a.loads.split(",") if v]:

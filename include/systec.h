@@ -326,6 +326,13 @@ typedef struct {
                              requests sharing steps with large ones */
   int32_t device;         /* HIP device ordinal */
   int32_t max_queue;      /* waiting requests before SYSTEC_EBUSY (<= 0: 2^20) */
+  int32_t max_inflight;   /* steps queued on the device at once (<= 0: 2; at most 4); a
+                             request admitted now starts after the steps
+                             already queued, so fewer steps lower latency and
+                             one step leaves the device idle between steps */
+  int32_t streams;        /* 1: the kernel kinds of a step run one after another on
+                             one stream; 0: one stream per kind (SSYMV, MTTKRP of
+                             order 3, 4, 5), so that the kinds overlap */
 } systec_serve_config;
 typedef struct {
   int64_t submitted, completed, failed, rejected, steps, queued, running;

@@ -176,16 +176,9 @@ constexpr int kPanelThreads = 1024;
 constexpr int kServeBlock = kPanelThreads;  // SSYMV step kernel
 constexpr int kServeMttkrpBlock = 256; // MTTKRP step kernel
 constexpr int kServeLds = kPanelRows * 4;  // bytes: the row sums of one panel
-// Work queues of the step launches on one stream: queue k's counter is
-// next[k * kQueueStride] (separate cache lines).
-constexpr int kStepQueues = 8;
-constexpr int kQueueStride = 64;
-struct StepCounter {
-  int next[kStepQueues * kQueueStride];
-};
-// Resets the queues of `nsets` counter sets and zeroes the outputs of newly
-// admitted requests; runs on a stream before its step launches.
-int launch_serve_prologue(const ZeroArgs& z, StepCounter* ctr, int nsets, hipStream_t s);
+// Zeroes the outputs of newly admitted requests; runs on a stream before
+// its step launches.
+int launch_serve_prologue(const ZeroArgs& z, hipStream_t s);
 // Step kernel variants: kind 0 is SSYMV (one variant); kinds 3, 4, 5 are
 // MTTKRP of that order, variant = 8 * (input is BF16) + 4 * (16-byte lanes:
 // R a multiple of 8 BF16 or 4 FP32 columns and the input 16-byte aligned) +
@@ -197,12 +190,10 @@ inline int step_variant(int dtype, int64_t R, const void* in) {
   const bool vec_lanes = R % vec == 0 && (reinterpret_cast<uintptr_t>(in) & 15) == 0;
   return (dtype == SYSTEC_BF16 ? 8 : 0) + (vec_lanes ? 4 : 0) + lane_class;
 }
-// Runs a persistent step kernel over the items of one (kind, variant) with
-// at most `grid` workgroups, taking items from the counter set `ctr`.
-int launch_serve_step(int kind, int variant, const StepArgs& a, int grid, StepCounter* ctr,
-                      hipStream_t s);
-// Workgroups of a step kernel that fit on one CU at once.
-int serve_blocks_per_cu(int kind, int variant, int* blocks);
+// Runs the step kernel of one (kind, variant): one workgroup per item.
+int launch_serve_step(int kind, int variant, const StepArgs& a, hipStream_t s);
+// Once per device before the first step: the SSYMV step kernel's LDS limit.
+int serve_init_kernels();
 
 // ---- multiplicity rule (host and device) ----------------------------------
 // For a sorted tuple of `order` indices whose equality pattern is `mask`

@@ -205,9 +205,11 @@ __device__ __forceinline__ void lds_view_slot(int t, int e0, int e1, const LdsVi
 }
 
 // W: slice width in columns (a multiple of the 16-byte vector, at most 64).
+// vec_rows: R is a multiple of the 16-byte vector and B is 16-byte aligned,
+// so the slice is staged in 16-byte pieces.
 template <int N, typename BT, int W>
 __global__ __launch_bounds__(kLdsThreads) void mttkrp_views_lds_kernel(
-    LdsViews vs, const BT* __restrict__ B, int R, int I, int nslices, int nchunks,
+    LdsViews vs, const BT* __restrict__ B, int R, int I, int nslices, int nchunks, int vec_rows,
     float* __restrict__ C) {
   constexpr int V = vec_of<BT>();
   constexpr int Lg = W / V;          // lanes per entry
@@ -220,10 +222,22 @@ __global__ __launch_bounds__(kLdsThreads) void mttkrp_views_lds_kernel(
 
   unsigned char* sB = lds;
   float* sCoef = reinterpret_cast<float*>(lds + static_cast<int64_t>(I) * kRowBytes);
-  BT* sBt = reinterpret_cast<BT*>(sB);
-  for (int q = threadIdx.x; q < I * W; q += kLdsThreads) {
-    const int i = q / W, c = col0 + (q - (q / W) * W);
-    sBt[q] = (c < R) ? B[static_cast<int64_t>(i) * R + c] : BT(0);
+  if (vec_rows) {
+    constexpr int kPieces = kRowBytes / 16;  // 16-byte pieces per staged row
+    uint4* s4 = reinterpret_cast<uint4*>(sB);
+    const int n = I * kPieces;
+#pragma unroll 4
+    for (int q = threadIdx.x; q < n; q += kLdsThreads) {
+      const int i = q / kPieces, c = col0 + (q - i * kPieces) * V;
+      s4[q] = (c < R) ? *reinterpret_cast<const uint4*>(B + static_cast<int64_t>(i) * R + c)
+                      : make_uint4(0u, 0u, 0u, 0u);
+    }
+  } else {
+    BT* sBt = reinterpret_cast<BT*>(sB);
+    for (int q = threadIdx.x; q < I * W; q += kLdsThreads) {
+      const int i = q / W, c = col0 + (q - (q / W) * W);
+      sBt[q] = (c < R) ? B[static_cast<int64_t>(i) * R + c] : BT(0);
+    }
   }
   if (threadIdx.x < 80) sCoef[threadIdx.x] = coef_table<N>().coef[threadIdx.x / 5][threadIdx.x % 5];
   __syncthreads();
@@ -295,7 +309,9 @@ int launch_lds_w(const LdsViews& vs, const BT* B, int R, int I, float* C, int cu
                                          static_cast<int>(lds)),
                      "hipFuncSetAttribute(dynamic LDS)");
   if (rc) return rc;
-  kern<<<dim3(nchunks * nslices), dim3(kLdsThreads), lds, s>>>(vs, B, R, I, nslices, nchunks, C);
+  const int vec_rows = (R % vec_of<BT>() == 0 && (reinterpret_cast<uintptr_t>(B) & 15) == 0) ? 1 : 0;
+  kern<<<dim3(nchunks * nslices), dim3(kLdsThreads), lds, s>>>(vs, B, R, I, nslices, nchunks,
+                                                               vec_rows, C);
   return check_launch("mttkrp LDS view kernel");
 }
 

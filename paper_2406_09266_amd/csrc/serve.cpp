@@ -54,24 +54,16 @@ void make_units(const Tensor* t, std::vector<serve::Unit>* units) {
 
 class GpuExecutor {
  public:
-  int init(int device, std::string* err) {
+  int init(int device, bool one_stream, std::string* err) {
     device_ = device;
     hipError_t e = hipSetDevice(device);
-    for (int k = 0; k < 4 && e == hipSuccess; ++k)
-      e = hipStreamCreateWithFlags(&streams_[k], hipStreamNonBlocking);
+    for (int k = 0; k < 4 && e == hipSuccess; ++k) {
+      if (one_stream && k > 0) streams_[k] = streams_[0];
+      else e = hipStreamCreateWithFlags(&streams_[k], hipStreamNonBlocking);
+    }
+    one_stream_ = one_stream;
     stream_ = streams_[0];
-    int cus = 0;
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
-    // persistent grids: as many workgroups as are resident at once
-    for (int k = 0; k < 4 && e == hipSuccess; ++k)
-      for (int v = 0; v < kStepVariants && e == hipSuccess; ++v) {
-        int per_cu = 0;
-        if (serve_blocks_per_cu(k == 0 ? 0 : k + 2, v, &per_cu) != SYSTEC_OK) e = hipErrorInvalidValue;
-        grid_[k][v] = std::max(1, cus) * std::max(1, per_cu);
-      }
-    // one counter set per (stream, variant)
-    if (e == hipSuccess)
-      e = hipMalloc(reinterpret_cast<void**>(&d_ctr_), 4 * kStepVariants * sizeof(StepCounter));
+    if (e == hipSuccess && serve_init_kernels() != SYSTEC_OK) e = hipErrorInvalidValue;
     for (int i = 0; i < kRing && e == hipSuccess; ++i)
       for (int k = 0; k < 4 && e == hipSuccess; ++k)
         e = hipEventCreateWithFlags(&ev_[i][k], hipEventDisableTiming);
@@ -88,9 +80,8 @@ class GpuExecutor {
     for (auto& evs : ev_)
       for (hipEvent_t ev : evs)
         if (ev) (void)hipEventDestroy(ev);
-    for (hipStream_t st : streams_)
-      if (st) (void)hipStreamDestroy(st);
-    if (d_ctr_) (void)hipFree(d_ctr_);
+    for (int k = 0; k < 4; ++k)
+      if (streams_[k] && !(one_stream_ && k > 0)) (void)hipStreamDestroy(streams_[k]);
   }
 
   // Builds the device descriptor and the unit table of an operand being
@@ -180,40 +171,22 @@ class GpuExecutor {
       for (int g = 0; g < 4 && !rc; ++g) {
         hipStream_t st = streams_[g];
         auto kind_of = [](const Tensor* t) { return t->kind == 0 ? 0 : t->order - 2; };
-        // outputs to zero, in batches of kStepReqs; each prologue also resets the
-        // stream's work queues, and one runs before every step launch
-        std::vector<ZeroArgs> zero;
-        for (size_t k = 0; k < plan.zero.size(); ++k) {
+        // outputs to zero, in batches of kStepReqs, before the kind's step
+        // launches (the step kernels add into them)
+        ZeroArgs z{};
+        for (size_t k = 0; k < plan.zero.size() && !rc; ++k) {
           const serve::Request* r = plan.zero[k];
           if (kind_of(static_cast<const Tensor*>(r->tensor->payload)) != g) continue;
-          if (zero.empty() || zero.back().n == kStepReqs) zero.push_back(ZeroArgs{});
-          ZeroArgs& z = zero.back();
           z.ptr[z.n] = r->out;
           z.count[z.n] = r->tensor->dim * (r->tensor->kind == 0 ? 1 : r->R);
-          ++z.n;
+          if (++z.n == kStepReqs) {
+            rc = launch_serve_prologue(z, st);
+            z = ZeroArgs{};
+          }
         }
-        // the last zero batch goes with the first prologue before a step
-        // launch; every prologue resets all counter sets of the stream
-        StepCounter* ctr = d_ctr_ + g * kStepVariants;
-        size_t zi = 0;
-        auto prologue = [&]() {
-          const ZeroArgs z = zi < zero.size() ? zero[zi++] : ZeroArgs{};
-          return launch_serve_prologue(z, ctr, kStepVariants, st);
-        };
-        while (!rc && zi + 1 < zero.size()) rc = prologue();
-        bool fresh = false;  // counters reset since the last launch of each variant
+        if (!rc && z.n) rc = launch_serve_prologue(z, st);
         for (int v = 0; v < kStepVariants && !rc; ++v) {
           StepArgs a{};
-          bool first_batch = true;
-          auto launch_step = [&]() {
-            int r = SYSTEC_OK;
-            if (!fresh || !first_batch) r = prologue();  // another batch of this variant
-            fresh = true;
-            first_batch = false;
-            if (!r) r = launch_serve_step(g == 0 ? 0 : g + 2, v, a, grid_[g][v], ctr + v, st);
-            a = StepArgs{};
-            return r;
-          };
           for (size_t k = 0; k < shares.size() && !rc; ++k) {
             const Share& sh = shares[k];
             if (kind_of(sh.t) != g) continue;
@@ -228,11 +201,13 @@ class GpuExecutor {
             q.R = static_cast<int32_t>(sh.req->R);
             q.dtype = sh.req->dtype;
             a.nitems += sh.count;
-            if (a.nreq == kStepReqs) rc = launch_step();
+            if (a.nreq == kStepReqs) {
+              rc = launch_serve_step(g == 0 ? 0 : g + 2, v, a, st);
+              a = StepArgs{};
+            }
           }
-          if (!rc && a.nreq) rc = launch_step();
+          if (!rc && a.nreq) rc = launch_serve_step(g == 0 ? 0 : g + 2, v, a, st);
         }
-        while (!rc && zi < zero.size()) rc = prologue();  // outputs with no work this step
         if (!rc) rc = check_hip(hipEventRecord(ev_[slot][g], st), "hipEventRecord");
       }
     }
@@ -278,10 +253,9 @@ class GpuExecutor {
 
  private:
   int device_ = 0;
-  int grid_[4][kStepVariants] = {};  // per stream (SSYMV, MTTKRP order 3, 4, 5) and variant
-  StepCounter* d_ctr_ = nullptr;      // [stream][variant]
   hipStream_t streams_[4] = {nullptr, nullptr, nullptr, nullptr};  // per kernel kind
   hipStream_t stream_ = nullptr;                                   // streams_[0]
+  bool one_stream_ = false;  // every kind on streams_[0], in order
   hipEvent_t ev_[kRing][4] = {};                                   // step done, per stream
 };
 
@@ -308,7 +282,7 @@ int systec_serve_create(const systec_serve_config* cfg, systec_server** out) {
   auto* s = new systec_server();
   s->exec.reset(new GpuExecutor());
   std::string err;
-  int rc = s->exec->init(cfg->device, &err);
+  int rc = s->exec->init(cfg->device, cfg->streams == 1, &err);
   if (rc) {
     delete s;
     return serve_fail(rc, err);
@@ -318,7 +292,7 @@ int systec_serve_create(const systec_serve_config* cfg, systec_server** out) {
   c.max_slots = cfg->max_slots;
   c.step_work = cfg->step_work_nnz;
   c.max_queue = cfg->max_queue > 0 ? cfg->max_queue : (1 << 20);
-  c.max_inflight = 3;
+  c.max_inflight = std::min(kRing, cfg->max_inflight > 0 ? cfg->max_inflight : 2);
   s->sched.reset(new serve::Scheduler<GpuExecutor>(c, *s->exec));
   *out = s;
   return SYSTEC_OK;

@@ -37,6 +37,8 @@
 #include <thread>
 #include <vector>
 
+#include <sys/prctl.h>
+
 namespace systec {
 namespace serve {
 
@@ -129,7 +131,12 @@ template <class Exec>
 class Scheduler {
  public:
   Scheduler(const Config& cfg, Exec& exec) : cfg_(cfg), exec_(exec) {
-    thread_ = std::thread([this] { loop(); });
+    thread_ = std::thread([this] {
+      // The loop polls in-flight steps with short timed waits; the default
+      // 50 us timer slack of a Linux thread would stretch each of them.
+      prctl(PR_SET_TIMERSLACK, 1000UL, 0UL, 0UL, 0UL);
+      loop();
+    });
   }
   ~Scheduler() { shutdown(); }
 

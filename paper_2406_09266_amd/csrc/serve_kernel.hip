@@ -1,20 +1,12 @@
-// The serving step: one launch per kernel kind runs the work of every request
-// admitted to the step (continuous batching): one for SSYMV and one per
-// MTTKRP order, on separate streams so that they overlap. The step's
-// requests and their unit ranges arrive as kernel arguments. The launches
-// are persistent: as many workgroups as fit on the device at once take items
-// from eight work queues until all are empty, and each item runs the same
-// device code as the standalone kernels.
-//
-// Work queues. Item i belongs to queue i mod 8; a queue is a counter that
-// hands out its items in order. Workgroup b starts on queue b mod 8 (blocks
-// are dispatched round-robin over the 8 XCDs, so a queue's items tend to stay
-// on one XCD) and moves on to the other queues when its own is empty. A
-// single counter serializes every workgroup of the chip on one address
-// (about 80 M atomics/s); eight counters on separate cache lines spread that
-// over eight. A prologue kernel on the same stream resets the counters
-// before every step launch, and zeroes the outputs of newly admitted
-// requests.
+// The serving step: one launch per kernel kind and variant runs the work of
+// every request admitted to the step (continuous batching). SSYMV and the
+// MTTKRP orders run on separate streams so that they overlap. The step's
+// requests and their unit ranges arrive as kernel arguments; workgroup b runs
+// item b (one work unit of one request) with the same device code as the
+// standalone kernels. Work units are short (a few microseconds), so the
+// hardware dispatcher balances the items and interleaves the workgroups of
+// the kinds that run at the same time; a prologue kernel on each stream
+// zeroes the outputs of newly admitted requests first.
 #include "common.h"
 #include "mttkrp_device.h"
 #include "panel_device.h"
@@ -24,9 +16,7 @@ namespace {
 
 using namespace dev;
 
-__global__ void serve_prologue_kernel(ZeroArgs z, StepCounter* ctr, int nsets) {
-  if (blockIdx.x == 0 && threadIdx.x < kStepQueues * nsets)
-    ctr[threadIdx.x / kStepQueues].next[(threadIdx.x % kStepQueues) * kQueueStride] = 0;
+__global__ void serve_prologue_kernel(ZeroArgs z) {
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
   const int64_t t0 = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   for (int s = 0; s < z.n; ++s) {
@@ -100,74 +90,38 @@ __device__ __forceinline__ void view_range(const ServeTensor* t, const ServeUnit
                                     0, q.R);
 }
 
-// Takes this workgroup's next item (uniform across the workgroup), or
-// returns n when every queue is empty. `q` is the queue being drained.
-__device__ __forceinline__ int take_item(StepCounter* c, int n, int* q, int* s_item) {
-  if (threadIdx.x == 0) {
-    int item = n;
-    for (int k = 0; k < kStepQueues; ++k) {
-      const int qq = (*q + k) & (kStepQueues - 1);
-      int* ctr = c->next + qq * kQueueStride;
-      // skip a drained queue without contending for its counter
-      if (k > 0 && __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) * kStepQueues +
-                           qq >= n)
-        continue;
-      const int i = atomicAdd(ctr, 1) * kStepQueues + qq;
-      if (i < n) {
-        item = i;
-        *q = qq;
-        break;
-      }
-    }
-    *s_item = item;
-  }
-  __syncthreads();
-  const int i = uni(*s_item);
-  __syncthreads();
-  return i;
-}
-
 // SSYMV items need the panel's row sums in LDS (1,024 threads, 128 KiB); MTTKRP
 // items need no LDS and run at full occupancy (256 threads, one kernel per
 // tensor order so that each keeps the registers of its own order); the four
 // waves of an MTTKRP workgroup share an item of a few tiles each.
-__global__ __launch_bounds__(kServeBlock) void serve_ssymv_kernel(StepArgs a, StepCounter* ctr) {
+__global__ __launch_bounds__(kServeBlock) void serve_ssymv_kernel(StepArgs a) {
   extern __shared__ float s_lds[];
-  __shared__ int s_item;
-  int q = blockIdx.x & (kStepQueues - 1);
-  for (int i = take_item(ctr, a.nitems, &q, &s_item); i < a.nitems;
-       i = take_item(ctr, a.nitems, &q, &s_item)) {
-    const StepReq& r = a.req[find_req(a, i)];
-    const ServeTensor* t = r.t;
-    const ServeUnit u = load_unit(t, r.unit0 + (i - r.item0));
-    const auto* pcol = uni_ptr(static_cast<const int32_t*>(t->p[0][0]));
-    const auto* prow = uni_ptr(static_cast<const uint16_t*>(t->p[0][1]));
-    const auto* pval = uni_ptr(static_cast<const float*>(t->p[0][2]));
-    const int dim = uni(t->dim), H = uni(t->H);
-    if (r.dtype == SYSTEC_F32)
-      ssymv_panel_chunk<float>(dim, H, u.a, u.b, u.c, pcol, prow, pval,
-                               static_cast<const float*>(r.in), r.out, s_lds);
-    else
-      ssymv_panel_chunk<uint16_t>(dim, H, u.a, u.b, u.c, pcol, prow, pval,
-                                  static_cast<const uint16_t*>(r.in), r.out, s_lds);
-  }
+  const int i = blockIdx.x;
+  const StepReq& r = a.req[find_req(a, i)];
+  const ServeTensor* t = r.t;
+  const ServeUnit u = load_unit(t, r.unit0 + (i - r.item0));
+  const auto* pcol = uni_ptr(static_cast<const int32_t*>(t->p[0][0]));
+  const auto* prow = uni_ptr(static_cast<const uint16_t*>(t->p[0][1]));
+  const auto* pval = uni_ptr(static_cast<const float*>(t->p[0][2]));
+  const int dim = uni(t->dim), H = uni(t->H);
+  if (r.dtype == SYSTEC_F32)
+    ssymv_panel_chunk<float>(dim, H, u.a, u.b, u.c, pcol, prow, pval,
+                             static_cast<const float*>(r.in), r.out, s_lds);
+  else
+    ssymv_panel_chunk<uint16_t>(dim, H, u.a, u.b, u.c, pcol, prow, pval,
+                                static_cast<const uint16_t*>(r.in), r.out, s_lds);
 }
 
 // One MTTKRP step kernel per (order, input dtype, lane layout, lane class),
 // so that each keeps only the registers of its own variant.
 template <int N, typename BT, int L, bool kVec>
-__global__ __launch_bounds__(kServeMttkrpBlock) void serve_mttkrp_kernel(StepArgs a,
-                                                                         StepCounter* ctr) {
-  __shared__ int s_item;
-  int q = blockIdx.x & (kStepQueues - 1);
-  for (int i = take_item(ctr, a.nitems, &q, &s_item); i < a.nitems;
-       i = take_item(ctr, a.nitems, &q, &s_item)) {
-    const StepReq& r = a.req[find_req(a, i)];
-    const ServeTensor* t = r.t;
-    const ServeUnit u = load_unit(t, r.unit0 + (i - r.item0));
-    if constexpr (kVec) view_range_vec<N, BT, L>(t, u, r);
-    else view_range<N, BT, L>(t, u, r);
-  }
+__global__ __launch_bounds__(kServeMttkrpBlock) void serve_mttkrp_kernel(StepArgs a) {
+  const int i = blockIdx.x;
+  const StepReq& r = a.req[find_req(a, i)];
+  const ServeTensor* t = r.t;
+  const ServeUnit u = load_unit(t, r.unit0 + (i - r.item0));
+  if constexpr (kVec) view_range_vec<N, BT, L>(t, u, r);
+  else view_range<N, BT, L>(t, u, r);
 }
 
 template <int N, typename BT, bool kVec>
@@ -193,54 +147,42 @@ const void* mttkrp_kernel_of(int variant) {
 }
 
 template <int N>
-hipError_t launch_mttkrp_variant(int variant, const StepArgs& a, dim3 g, StepCounter* ctr,
-                                 hipStream_t s) {
+hipError_t launch_mttkrp_variant(int variant, const StepArgs& a, dim3 g, hipStream_t s) {
   const void* k = mttkrp_kernel_of<N>(variant);
-  void* args[] = {const_cast<StepArgs*>(&a), &ctr};
+  void* args[] = {const_cast<StepArgs*>(&a)};
   return hipLaunchKernel(k, g, dim3(kServeMttkrpBlock), args, 0, s);
 }
 
 }  // namespace
 
-int launch_serve_prologue(const ZeroArgs& z, StepCounter* ctr, int nsets, hipStream_t s) {
+int launch_serve_prologue(const ZeroArgs& z, hipStream_t s) {
   int64_t total = 0;
   for (int k = 0; k < z.n; ++k) total += z.count[k];
+  if (total == 0) return SYSTEC_OK;
   const int grid = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>((total / 4 + 255) / 256, 2048)));
-  serve_prologue_kernel<<<dim3(grid), dim3(256), 0, s>>>(z, ctr, nsets);
+  serve_prologue_kernel<<<dim3(grid), dim3(256), 0, s>>>(z);
   return check_launch("serve prologue kernel");
 }
 
-int launch_serve_step(int kind, int variant, const StepArgs& a, int grid, StepCounter* ctr,
-                      hipStream_t s) {
+int launch_serve_step(int kind, int variant, const StepArgs& a, hipStream_t s) {
   if (a.nitems == 0) return SYSTEC_OK;
-  const dim3 g(std::max(1, std::min(grid, a.nitems)));
+  const dim3 g(a.nitems);
   hipError_t e = hipSuccess;
   switch (kind) {
-    case 0: serve_ssymv_kernel<<<g, dim3(kServeBlock), kServeLds, s>>>(a, ctr); break;  // LDS limit set by serve_blocks_per_cu
-    case 3: e = launch_mttkrp_variant<3>(variant, a, g, ctr, s); break;
-    case 4: e = launch_mttkrp_variant<4>(variant, a, g, ctr, s); break;
-    default: e = launch_mttkrp_variant<5>(variant, a, g, ctr, s); break;
+    case 0: serve_ssymv_kernel<<<g, dim3(kServeBlock), kServeLds, s>>>(a); break;  // LDS limit set by serve_init_kernels
+    case 3: e = launch_mttkrp_variant<3>(variant, a, g, s); break;
+    case 4: e = launch_mttkrp_variant<4>(variant, a, g, s); break;
+    default: e = launch_mttkrp_variant<5>(variant, a, g, s); break;
   }
   if (e != hipSuccess) return check_hip(e, "serve mttkrp kernel launch");
   return check_launch(kind == 0 ? "serve ssymv kernel" : "serve mttkrp kernel");
 }
 
-int serve_blocks_per_cu(int kind, int variant, int* blocks) {
-  hipError_t e;
-  if (kind == 0) {
-    // more than the default 64 KiB of dynamic LDS (set once, before any launch)
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(serve_ssymv_kernel),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, kServeLds);
-    if (e == hipSuccess)
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, serve_ssymv_kernel, kServeBlock,
-                                                       kServeLds);
-  } else {
-    const void* k = kind == 3 ? mttkrp_kernel_of<3>(variant)
-                    : kind == 4 ? mttkrp_kernel_of<4>(variant)
-                                : mttkrp_kernel_of<5>(variant);
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k, kServeMttkrpBlock, 0);
-  }
-  return check_hip(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+int serve_init_kernels() {
+  // more than the default 64 KiB of dynamic LDS (set once, before any launch)
+  return check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(serve_ssymv_kernel),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, kServeLds),
+                   "hipFuncSetAttribute(dynamic LDS)");
 }
 
 }  // namespace systec

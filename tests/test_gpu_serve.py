@@ -82,11 +82,13 @@ def _oracle(mats, tens, req, bf16):
     return oracle.mttkrp(t["order"], t["dim"], t["idx"].T, f32(t["val"]), ref)[0]
 
 
-@pytest.mark.parametrize("bf16", [False, True])
-def test_mix_equals_alone_and_oracle(bf16):
+@pytest.mark.parametrize("bf16,streams,inflight", [(False, 0, 0), (True, 0, 0), (True, 1, 1),
+                                                    (True, 1, 3)])
+def test_mix_equals_alone_and_oracle(bf16, streams, inflight):
     mats, tens = _pool()
     reqs = _requests(mats, tens, 24, seed=5)
-    with systec.Server(budget_bytes=8 << 30, max_slots=8, step_work_nnz=1 << 17) as srv:
+    with systec.Server(budget_bytes=8 << 30, max_slots=8, step_work_nnz=1 << 17,
+                       streams=streams, max_inflight=inflight) as srv:
         ids = _register(srv, mats, tens)
         # alone: one request at a time
         alone = []
