@@ -52,6 +52,10 @@ def parse():
                     help="served_mix: requests running at once")
     ap.add_argument("--max-inflight", type=int, default=0,
                     help="served_mix: steps queued on the device at once (0: the server default)")
+    ap.add_argument("--served-dtype", default="bf16", choices=["bf16", "f32"],
+                    help="served_mix: input dtype of the served requests (the plain form is FP32)")
+    ap.add_argument("--min-step-work", type=int, default=0,
+                    help="served_mix: step budget with one running request (0: fixed steps)")
     ap.add_argument("--streams", type=int, default=0,
                     help="served_mix: 1 runs a step's kernel kinds in order on one stream, "
                          "0 one stream per kind")
@@ -391,7 +395,8 @@ def served_mix(a, torch, systec, synth, dev):
 
     budget = 200 << 30
     srv = systec.Server(budget_bytes=budget, max_slots=a.max_slots, step_work_nnz=a.step_work,
-                        max_inflight=a.max_inflight, streams=a.streams)
+                        max_inflight=a.max_inflight, streams=a.streams,
+                        min_step_work_nnz=a.min_step_work)
     ids = [srv.register(t) for t in served_t]
 
     def out_for(p, R):
@@ -406,7 +411,7 @@ def served_mix(a, torch, systec, synth, dev):
             due = base + int(t_arr * 1e9)
             while systec.Server.now_ns() < due:
                 pass
-            x = inputs[(p, R)][1]
+            x = inputs[(p, R)][0 if a.served_dtype == "f32" else 1]
             outs.append(srv.submit(ids[p], x, out_for(p, R), arrival_ns=due))
         for rid in outs:
             srv.wait(rid, 600_000_000)
@@ -463,7 +468,8 @@ def served_mix(a, torch, systec, synth, dev):
                         "vs plain FP32 one request at a time",
               "workload": "served_mix", "n_gpus": 1, "data": "synthetic (device generators)",
               "server": {"max_slots": a.max_slots, "step_work_nnz": a.step_work,
-                         "max_inflight": a.max_inflight or 2, "streams": a.streams},
+                         "max_inflight": a.max_inflight or 2, "streams": a.streams,
+                         "min_step_work_nnz": a.min_step_work, "input_dtype": a.served_dtype},
               "pool": {"tensors": len(pool), "per_kind": K, "resident_bytes": resident,
                        "budget_bytes": budget, "effective_nnz_total": int(sum(eff)),
                        "generate_s": round(t_gen, 2), "prepare_s": round(t_prep, 2)},

@@ -294,9 +294,9 @@ SYSTEC_API int systec_mttkrp_t_ex(const systec_tensor* t, const void* B, systec_
 
 /* ------------------------------------------------------------------------
  * Serving: many prepared operands resident in HBM, requests of mixed kind
- * and size batched continuously into persistent launches.
+ * and size batched continuously into step launches.
  *
- * A server owns a stream on `device` and a scheduler thread. Registered
+ * A server owns streams on `device` and a scheduler thread. Registered
  * tensors (systec_serve_register takes ownership of a systec_tensor; it is
  * freed by the server) count against budget_bytes while registered. A
  * request names a registered tensor, an input (x for a matrix, B with R
@@ -307,7 +307,8 @@ SYSTEC_API int systec_mttkrp_t_ex(const systec_tensor* t, const void* B, systec_
  * SYSTEC_EBUDGET from submit, and more than max_queue waiting requests
  * return SYSTEC_EBUSY. Each step takes work (chunks of the prepared
  * operands, at most step_work_nnz entries in total) from every running
- * request round-robin and runs it as one persistent kernel launch; a
+ * request round-robin and runs it as one launch per kernel kind and
+ * variant, one workgroup per work unit; a
  * request submitted while a step runs joins the next step. The output is
  * zeroed by the server; it is complete when wait returns SYSTEC_OK or poll
  * reports state 2. Latency is measured from arrival_ns (a time from
@@ -333,6 +334,9 @@ typedef struct {
   int32_t streams;        /* 1: the kernel kinds of a step run one after another on
                              one stream; 0: one stream per kind (SSYMV, MTTKRP of
                              order 3, 4, 5), so that the kinds overlap */
+  int64_t min_step_work_nnz; /* work per step with one running request; the step
+                                budget grows linearly to step_work_nnz with
+                                max_slots running (<= 0: always step_work_nnz) */
 } systec_serve_config;
 typedef struct {
   int64_t submitted, completed, failed, rejected, steps, queued, running;

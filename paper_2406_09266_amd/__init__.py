@@ -350,17 +350,19 @@ class Server:
     QUEUED, RUNNING, DONE, FAILED = 0, 1, 2, 3
 
     def __init__(self, budget_bytes=200 << 30, max_slots=32, step_work_nnz=1 << 27, device=None,
-                 max_queue=0, max_inflight=0, streams=0):
+                 max_queue=0, max_inflight=0, streams=0, min_step_work_nnz=0):
         """step_work_nnz: entries per step; larger steps raise throughput
         (2^27 measured best at saturation on a mixed workload), smaller ones
         lower the latency of small requests that share steps with large ones.
         max_inflight: steps queued on the device at once (0: the default, 2).
         streams: 1 runs the kernel kinds of a step one after another on one
-        stream; 0 gives each kind its own stream."""
+        stream; 0 gives each kind its own stream.
+        min_step_work_nnz: step budget with one running request, growing
+        linearly to step_work_nnz with max_slots running (0: fixed steps)."""
         torch = _torch()
         cfg = _lib.ServeConfig(budget_bytes, max_slots, step_work_nnz,
                                torch.cuda.current_device() if device is None else device,
-                               max_queue, max_inflight, streams)
+                               max_queue, max_inflight, streams, min_step_work_nnz)
         self._h = ctypes.c_void_p()
         call("systec_serve_create", ctypes.byref(cfg), ctypes.byref(self._h))
         self._live = {}

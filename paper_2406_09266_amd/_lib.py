@@ -62,7 +62,7 @@ class ServeConfig(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_uint64), ("max_slots", ctypes.c_int32),
                 ("step_work_nnz", ctypes.c_int64), ("device", ctypes.c_int32),
                 ("max_queue", ctypes.c_int32), ("max_inflight", ctypes.c_int32),
-                ("streams", ctypes.c_int32)]
+                ("streams", ctypes.c_int32), ("min_step_work_nnz", ctypes.c_int64)]
 
 
 class ServeStats(ctypes.Structure):

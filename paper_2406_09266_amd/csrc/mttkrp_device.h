@@ -35,6 +35,41 @@ struct IdxPtrs {
   const int32_t* p[5];
 };
 
+// The coefficients of one output slot T, coef[mask][T] for every equality
+// mask of order N, packed 8 bits per mask into two 64-bit constants (masks
+// 0..7 and 8..15). They are integers from 0 to 24 (the largest is 5!/5 for
+// five distinct indices), so a view kernel, whose slot is a template
+// parameter, reads its coefficient with a shift instead of a memory load.
+template <int N, int T>
+constexpr uint64_t packed_slot_coef(int half) {
+  const CoefTable t = make_coef_table(N);
+  uint64_t w = 0;
+  for (int k = 0; k < 8; ++k) {
+    const float c = t.coef[half * 8 + k][T];
+    w |= static_cast<uint64_t>(static_cast<uint32_t>(c)) << (8 * k);
+  }
+  return w;
+}
+
+template <int N, int T>
+constexpr bool slot_coef_packable() {
+  const CoefTable t = make_coef_table(N);
+  for (int m = 0; m < 16; ++m) {
+    const float c = t.coef[m][T];
+    if (c < 0.0f || c > 255.0f || c != static_cast<float>(static_cast<uint32_t>(c))) return false;
+  }
+  return true;
+}
+
+template <int N, int T>
+__device__ __forceinline__ float slot_coef(int mask) {
+  static_assert(slot_coef_packable<N, T>(), "slot coefficients must be integers in 0..255");
+  constexpr uint64_t lo = packed_slot_coef<N, T>(0);
+  constexpr uint64_t hi = packed_slot_coef<N, T>(1);
+  const uint64_t w = (N < 5 || mask < 8) ? lo : hi;
+  return static_cast<float>(static_cast<uint32_t>(w >> (8 * (mask & 7))) & 0xffu);
+}
+
 // Leave-one-out products: loo[t] = prod_{s != t} b[s].
 template <int N>
 __device__ __forceinline__ void leave_one_out(const float (&b)[N], float (&loo)[N]) {
@@ -170,7 +205,7 @@ __device__ __forceinline__ void mttkrp_view_tile(int e0, int e1, const IdxPtrs& 
 #pragma unroll
       for (int s = 0; s < N; ++s)
         if (s != T) p *= b[u][s];
-      const float k = coef_table<N>().coef[equality_mask_of(c[u], N)][T];
+      const float k = slot_coef<N, T>(equality_mask_of(c[u], N));
       const int out = c[u][T];
       if (out != cur) {
         if (cur >= 0 && lc.col_ok)
@@ -315,7 +350,7 @@ __device__ __forceinline__ void mttkrp_view_range_vec(int e0, int e1, const IdxP
     float p[kUnrollVec][V];
 #pragma unroll
     for (int u = 0; u < kUnrollVec; ++u) {
-      const float kv = ok[u] ? coef_table<N>().coef[equality_mask_of(c[u], N)][T] * v[u] : 0.0f;
+      const float kv = ok[u] ? slot_coef<N, T>(equality_mask_of(c[u], N)) * v[u] : 0.0f;
 #pragma unroll
       for (int j = 0; j < V; ++j) p[u][j] = kv;
 #pragma unroll

@@ -1,13 +1,12 @@
 // Serving runtime: the GPU executor behind the scheduler core (serve_core.h)
 // and the systec_serve_* entry points.
 //
-// Each step copies its work items from a ring of pinned host buffers to the
-// device, then issues one zero kernel for the outputs of newly admitted
-// requests and the persistent step kernels (SSYMV items with the panel row
-// sums in LDS on the first stream; MTTKRP items, one kernel per tensor
-// order, each on a stream of its own), every stream closed by an event. Up to
-// three steps are in flight, so the host builds the next step while others
-// run.
+// A step issues, on one stream per kernel kind (SSYMV; MTTKRP of order 3,
+// 4, 5), a zero kernel for the outputs of the kind's newly admitted requests
+// and then its step kernels (one per variant, one workgroup per work item;
+// the requests and their unit ranges travel as kernel arguments), each
+// stream closed by an event. A few steps are in flight (max_inflight), so
+// the host builds the next step while others run.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -173,6 +172,7 @@ class GpuExecutor {
         auto kind_of = [](const Tensor* t) { return t->kind == 0 ? 0 : t->order - 2; };
         // outputs to zero, in batches of kStepReqs, before the kind's step
         // launches (the step kernels add into them)
+        int launched = 0;
         ZeroArgs z{};
         for (size_t k = 0; k < plan.zero.size() && !rc; ++k) {
           const serve::Request* r = plan.zero[k];
@@ -182,9 +182,13 @@ class GpuExecutor {
           if (++z.n == kStepReqs) {
             rc = launch_serve_prologue(z, st);
             z = ZeroArgs{};
+            ++launched;
           }
         }
-        if (!rc && z.n) rc = launch_serve_prologue(z, st);
+        if (!rc && z.n) {
+          rc = launch_serve_prologue(z, st);
+          ++launched;
+        }
         for (int v = 0; v < kStepVariants && !rc; ++v) {
           StepArgs a{};
           for (size_t k = 0; k < shares.size() && !rc; ++k) {
@@ -204,11 +208,18 @@ class GpuExecutor {
             if (a.nreq == kStepReqs) {
               rc = launch_serve_step(g == 0 ? 0 : g + 2, v, a, st);
               a = StepArgs{};
+              ++launched;
             }
           }
-          if (!rc && a.nreq) rc = launch_serve_step(g == 0 ? 0 : g + 2, v, a, st);
+          if (!rc && a.nreq) {
+            rc = launch_serve_step(g == 0 ? 0 : g + 2, v, a, st);
+            ++launched;
+          }
         }
-        if (!rc) rc = check_hip(hipEventRecord(ev_[slot][g], st), "hipEventRecord");
+        // a stream with no work this step records no event (queries of it
+        // report done)
+        used_[slot][g] = launched != 0;
+        if (!rc && used_[slot][g]) rc = check_hip(hipEventRecord(ev_[slot][g], st), "hipEventRecord");
       }
     }
     if (rc) {
@@ -222,6 +233,7 @@ class GpuExecutor {
   int part_of(const serve::TensorEntry& t) const { return t.kind == 0 ? 0 : t.order - 2; }
 
   int query_part(int64_t step_id, int part, std::string* err) {
+    if (!used_[step_id % kRing][part]) return 1;
     const hipError_t e = hipEventQuery(ev_[step_id % kRing][part]);
     if (e == hipErrorNotReady) return 0;
     if (e != hipSuccess) {
@@ -233,8 +245,9 @@ class GpuExecutor {
 
   int query(int64_t step_id, std::string* err) {
     const int slot = static_cast<int>(step_id % kRing);
-    for (hipEvent_t ev : ev_[slot]) {
-      const hipError_t e = hipEventQuery(ev);
+    for (int g = 0; g < 4; ++g) {
+      if (!used_[slot][g]) continue;
+      const hipError_t e = hipEventQuery(ev_[slot][g]);
       if (e == hipErrorNotReady) return 0;
       if (e != hipSuccess) {
         *err = std::string("serving step failed: ") + hipGetErrorString(e);
@@ -257,6 +270,7 @@ class GpuExecutor {
   hipStream_t stream_ = nullptr;                                   // streams_[0]
   bool one_stream_ = false;  // every kind on streams_[0], in order
   hipEvent_t ev_[kRing][4] = {};                                   // step done, per stream
+  bool used_[kRing][4] = {};  // the step slot's stream had work (recorded its event)
 };
 
 }  // namespace
@@ -291,6 +305,7 @@ int systec_serve_create(const systec_serve_config* cfg, systec_server** out) {
   c.budget_bytes = cfg->budget_bytes;
   c.max_slots = cfg->max_slots;
   c.step_work = cfg->step_work_nnz;
+  c.min_step_work = cfg->min_step_work_nnz;
   c.max_queue = cfg->max_queue > 0 ? cfg->max_queue : (1 << 20);
   c.max_inflight = std::min(kRing, cfg->max_inflight > 0 ? cfg->max_inflight : 2);
   s->sched.reset(new serve::Scheduler<GpuExecutor>(c, *s->exec));

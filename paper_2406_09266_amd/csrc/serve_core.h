@@ -63,7 +63,13 @@ inline double percentile_sorted(const std::vector<double>& v, double p) {
 struct Config {
   uint64_t budget_bytes = 0;
   int max_slots = 16;
-  int64_t step_work = 1 << 24;  // entries per step
+  int64_t step_work = 1 << 24;  // entries per step (at most)
+  // Entries per step with few running requests: the budget grows linearly
+  // from min_step_work (one running request) to step_work (max_slots
+  // running). Short steps while the device has room keep a newly arrived
+  // request from waiting behind a long step; full steps under load keep the
+  // per-step costs small. <= 0: always step_work.
+  int64_t min_step_work = 0;
   int max_queue = 1 << 20;
   int max_inflight = 3;         // steps in flight (build step s+1 while s runs)
 };
@@ -132,8 +138,8 @@ class Scheduler {
  public:
   Scheduler(const Config& cfg, Exec& exec) : cfg_(cfg), exec_(exec) {
     thread_ = std::thread([this] {
-      // The loop polls in-flight steps with short timed waits; the default
-      // 50 us timer slack of a Linux thread would stretch each of them.
+      // The loop's timed waits are short; the default 50 us timer slack of a
+      // Linux thread would stretch each of them.
       prctl(PR_SET_TIMERSLACK, 1000UL, 0UL, 0UL, 0UL);
       loop();
     });
@@ -346,8 +352,18 @@ class Scheduler {
   // not stuck behind large ones); the rest goes to the running requests in
   // admission order (a large request keeps most of the device, as it would
   // alone). Every running request with work left gets at least one unit.
+  int64_t step_budget_locked() const {
+    if (cfg_.min_step_work <= 0 || cfg_.min_step_work >= cfg_.step_work) return cfg_.step_work;
+    const int64_t live = static_cast<int64_t>(active_.size());
+    const int64_t slots = std::max(1, cfg_.max_slots);
+    const int64_t span = cfg_.step_work - cfg_.min_step_work;
+    return cfg_.min_step_work + span * std::min<int64_t>(std::max<int64_t>(live - 1, 0), slots - 1) /
+                                    std::max<int64_t>(slots - 1, 1);
+  }
+
   void fill_locked(Plan& plan, std::vector<std::shared_ptr<Request>>& touched) {
-    int64_t budget = cfg_.step_work;
+    const int64_t step_work = step_budget_locked();
+    int64_t budget = step_work;
     // Takes the request's next units up to `limit` entries (and the step's
     // remaining budget), the unit that crosses the limit included; with
     // at_least_one, one unit even when the budget is spent.
@@ -377,7 +393,7 @@ class Scheduler {
       }
     };
     const int64_t live = std::max<int64_t>(1, static_cast<int64_t>(active_.size()));
-    const int64_t share = std::max<int64_t>(1, cfg_.step_work / (2 * live));
+    const int64_t share = std::max<int64_t>(1, step_work / (2 * live));
     for (auto& r : active_) take(r, share, true);
     for (auto& r : active_) {
       if (budget <= 0) break;
@@ -495,9 +511,14 @@ class Scheduler {
         done_cv_.notify_all();
         continue;
       }
-      // 3. nothing to do right now
+      // 3. nothing to do right now. With steps in flight the loop polls
+      // their events without sleeping (a completed request is noticed within
+      // microseconds; this thread occupies one host core while the device
+      // works); idle, it sleeps until a submit wakes it.
       if (!inflight_.empty()) {
-        wake_.wait_until(lk, deadline(std::chrono::microseconds(20)));
+        lk.unlock();
+        std::this_thread::yield();
+        lk.lock();
       } else if (queue_.empty() || static_cast<int>(active_.size()) >= cfg_.max_slots ||
                  bytes_in_use_ + queue_.front()->bytes > cfg_.budget_bytes) {
         if (stop_ && queue_.empty() && active_.empty()) continue;

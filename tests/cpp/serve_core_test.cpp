@@ -351,6 +351,47 @@ void test_every_running_request_progresses() {
   std::printf("PASS every_running_request_progresses\n");
 }
 
+// With min_step_work set, a lone request runs in short steps, and the step
+// budget grows with the number of running requests up to step_work.
+void test_step_budget_grows_with_load() {
+  FakeExec ex;
+  ex.delay_us = 50;
+  Config c;
+  c.budget_bytes = 1 << 30;
+  c.max_slots = 5;
+  c.step_work = 1000;
+  c.min_step_work = 200;
+  Scheduler<FakeExec> s(c, ex);
+  int64_t tid;
+  std::string err;
+  CHECK(s.register_tensor(tensor(1, 100, 100, 10), &tid, &err) == kOk);
+  int64_t r;
+  CHECK(s.submit(tid, &ex, 0, 4, reinterpret_cast<float*>(&ex), 0, &r, &err) == kOk);
+  CHECK(s.wait(r, 5000000, &err) == kOk);
+  {
+    std::lock_guard<std::mutex> lk(ex.mu);
+    // one running request: 200 entries (20 units) per step
+    for (size_t k = 0; k + 1 < ex.step_reqs.size(); ++k) CHECK(ex.step_reqs[k].size() == 20);
+    CHECK(ex.step_reqs.size() == 5);
+    ex.step_reqs.clear();
+  }
+  // five at once: the first step has all five running, so its budget is
+  // the full 1000 entries
+  std::vector<int64_t> ids;
+  for (int i = 0; i < 5; ++i) {
+    CHECK(s.submit(tid, &ex, 0, 4, reinterpret_cast<float*>(&ex), 0, &r, &err) == kOk);
+    ids.push_back(r);
+  }
+  for (auto q : ids) CHECK(s.wait(q, 5000000, &err) == kOk);
+  {
+    std::lock_guard<std::mutex> lk(ex.mu);
+    size_t most = 0;
+    for (auto& v : ex.step_reqs) most = std::max(most, v.size());
+    CHECK(most == 100);  // 1000 entries of 10-entry units
+  }
+  std::printf("PASS step_budget_grows_with_load\n");
+}
+
 int main() {
   test_percentiles();
   test_basic_all_units_once();
@@ -361,6 +402,7 @@ int main() {
   test_failure_and_timeout();
   test_shutdown_cancels_queue();
   test_concurrent_submitters();
+  test_step_budget_grows_with_load();
   std::printf("ALL PASS\n");
   return 0;
 }
