@@ -91,6 +91,7 @@ int expand_coo(int order, int64_t I, int64_t nnz, const int32_t* const* idx, con
 // starts a run of equal indices, sorted by their slot-t index (stable), so
 // that every output update of view t is a segmented reduction.
 constexpr int kPanelTile = 512;
+constexpr int64_t kShortRun = 64;
 struct ServeTensor;
 struct ServeUnit;
 struct Tensor {
@@ -114,6 +115,12 @@ struct Tensor {
   std::vector<int32_t> h_chunk_panel, h_chunk_tile_begin, h_chunk_tile_end;  // host copies
   // tensor
   int64_t vnnz[5] = {0, 0, 0, 0, 0};
+  // Fewer than kShortRun stored entries per index on average: the views' runs
+  // of equal output rows are short, and the view kernels take one lane per
+  // column (each entry one contiguous row update) instead of vector lanes
+  // (one update per lane column for every entry of a run shorter than an
+  // iteration).
+  bool short_runs = false;
   int32_t* vidx[5][5] = {};
   float* vval[5] = {};
   // serving (built at registration)
@@ -180,14 +187,27 @@ constexpr int kServeLds = kPanelRows * 4;  // bytes: the row sums of one panel
 // its step launches.
 int launch_serve_prologue(const ZeroArgs& z, hipStream_t s);
 // Step kernel variants: kind 0 is SSYMV (one variant); kinds 3, 4, 5 are
-// MTTKRP of that order, variant = 8 * (input is BF16) + 4 * (16-byte lanes:
-// R a multiple of 8 BF16 or 4 FP32 columns and the input 16-byte aligned) +
-// lane class (R <= 8, 16, 32, 64).
+// MTTKRP of that order, variant = 8 * (input is BF16) + 4 * (vector lanes:
+// the operand's runs are not short, R is a multiple of the class's lane width
+// and the input is aligned to it) + lane class (R <= 8, 16, 32, 64).
 constexpr int kStepVariants = 16;
-inline int step_variant(int dtype, int64_t R, const void* in) {
+// Lane width (columns per lane) of the MTTKRP vector-lane kernels for a block
+// of `cols` columns of a factor with R columns of `elem_bytes`-byte elements:
+// the widest of 8, 4, 2 columns that fits 16 bytes, divides R and leaves at
+// least four lanes per row (two for blocks narrower than eight columns); 0 if
+// R is odd (no vector lanes).
+constexpr int lane_vec_width(int cols, int64_t R, int elem_bytes) {
+  for (int v = 8; v >= 2; v /= 2)
+    if (v * elem_bytes <= 16 && R % v == 0 && (v * 4 <= cols || v == 2)) return v;
+  return 0;
+}
+inline int step_variant(int dtype, int64_t R, const void* in, bool short_runs) {
   const int lane_class = R <= 8 ? 0 : R <= 16 ? 1 : R <= 32 ? 2 : 3;
-  const int vec = dtype == SYSTEC_BF16 ? 8 : 4;
-  const bool vec_lanes = R % vec == 0 && (reinterpret_cast<uintptr_t>(in) & 15) == 0;
+  const int esize = dtype == SYSTEC_BF16 ? 2 : 4;
+  const int L = 8 << lane_class;
+  const int V = lane_vec_width(L, L, esize);  // the lane width of the class's kernel
+  const bool vec_lanes = !short_runs && V != 0 && R % V == 0 &&
+                         reinterpret_cast<uintptr_t>(in) % static_cast<uintptr_t>(V * esize) == 0;
   return (dtype == SYSTEC_BF16 ? 8 : 0) + (vec_lanes ? 4 : 0) + lane_class;
 }
 // Runs the step kernel of one (kind, variant): one workgroup per item.

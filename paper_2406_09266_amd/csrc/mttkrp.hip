@@ -87,11 +87,11 @@ __global__ __launch_bounds__(kBlock) void mttkrp_views_kernel(ViewSet vs,
   }
 }
 
-// The same launch with 16-byte lanes (mttkrp_device.h): one wave per range
-// of kTileVec entries of a view.
+// The same launch with vector lanes (mttkrp_device.h): one wave per range
+// of kTileVec entries of a view; V columns per lane, Lg lanes per row.
 constexpr int kTileVec = 1024;
 
-template <int N, typename BT, int Lg, int T>
+template <int N, typename BT, int V, int Lg, int T>
 __device__ __forceinline__ void vec_block(const ViewSet& vs, int b, const BT* __restrict__ B,
                                           int ldb, float* __restrict__ C, int ldc, int col0,
                                           int ncols) {
@@ -99,25 +99,25 @@ __device__ __forceinline__ void vec_block(const ViewSet& vs, int b, const BT* __
   const int64_t e0 = wave * kTileVec;
   if (e0 >= vs.nnz[T]) return;
   const int e1 = static_cast<int>(min<int64_t>(vs.nnz[T], e0 + kTileVec));
-  mttkrp_view_range_vec<N, BT, Lg, T>(static_cast<int>(e0), e1, vs.idx[T], vs.val[T], B, ldb, C,
-                                      ldc, col0, ncols);
+  mttkrp_view_range_vec<N, BT, V, Lg, T>(static_cast<int>(e0), e1, vs.idx[T], vs.val[T], B, ldb,
+                                         C, ldc, col0, ncols);
 }
 
-template <int N, typename BT, int Lg>
+template <int N, typename BT, int V, int Lg>
 __global__ __launch_bounds__(kBlock) void mttkrp_views_vec_kernel(ViewSet vs,
                                                                 const BT* __restrict__ B, int ldb,
                                                                 float* __restrict__ C, int ldc,
                                                                 int col0, int ncols) {
   const int b = blockIdx.x;
   if (b < vs.block0[1]) {
-    vec_block<N, BT, Lg, 0>(vs, b, B, ldb, C, ldc, col0, ncols);
+    vec_block<N, BT, V, Lg, 0>(vs, b, B, ldb, C, ldc, col0, ncols);
   } else if (b < vs.block0[2]) {
-    vec_block<N, BT, Lg, 1>(vs, b, B, ldb, C, ldc, col0, ncols);
+    vec_block<N, BT, V, Lg, 1>(vs, b, B, ldb, C, ldc, col0, ncols);
   } else if (N == 3 || b < vs.block0[3]) {
-    vec_block<N, BT, Lg, 2>(vs, b, B, ldb, C, ldc, col0, ncols);
+    vec_block<N, BT, V, Lg, 2>(vs, b, B, ldb, C, ldc, col0, ncols);
   } else if constexpr (N > 3) {
-    if (N == 4 || b < vs.block0[4]) vec_block<N, BT, Lg, 3>(vs, b, B, ldb, C, ldc, col0, ncols);
-    else if constexpr (N > 4) vec_block<N, BT, Lg, 4>(vs, b, B, ldb, C, ldc, col0, ncols);
+    if (N == 4 || b < vs.block0[4]) vec_block<N, BT, V, Lg, 3>(vs, b, B, ldb, C, ldc, col0, ncols);
+    else if constexpr (N > 4) vec_block<N, BT, V, Lg, 4>(vs, b, B, ldb, C, ldc, col0, ncols);
   }
 }
 
@@ -210,32 +210,57 @@ ViewSet view_set(const Tensor* tn, int tile) {
   return vs;
 }
 
-template <int N, typename BT, int Lg>
+template <int N, typename BT, int V, int Lg>
 void launch_vec_cols(const ViewSet& vs, const BT* B, int R, float* C, int col0, int ncols,
                      hipStream_t s) {
-  mttkrp_views_vec_kernel<N, BT, Lg>
+  mttkrp_views_vec_kernel<N, BT, V, Lg>
       <<<dim3(vs.block0[N]), dim3(kBlock), 0, s>>>(vs, B, R, C, R, col0, ncols);
 }
 
-// 16-byte lanes when rows are 16-byte aligned (R a multiple of the vector
-// and B 16-byte aligned), else one lane per column.
+// One column block with V columns per lane; false if its lane count has no
+// kernel (the caller then takes the lane-per-column kernel).
+template <int N, typename BT, int V>
+bool launch_vec_block(const ViewSet& vs, const BT* B, int R, float* C, int c0, int w,
+                      hipStream_t s) {
+  int lanes = 1;
+  while (lanes * V < w) lanes *= 2;
+  switch (lanes) {
+    case 1: launch_vec_cols<N, BT, V, 1>(vs, B, R, C, c0, w, s); return true;
+    case 2: launch_vec_cols<N, BT, V, 2>(vs, B, R, C, c0, w, s); return true;
+    case 4: launch_vec_cols<N, BT, V, 4>(vs, B, R, C, c0, w, s); return true;
+    case 8: launch_vec_cols<N, BT, V, 8>(vs, B, R, C, c0, w, s); return true;
+    default:
+      if constexpr (V == 4) {
+        launch_vec_cols<N, BT, V, 16>(vs, B, R, C, c0, w, s);
+        return true;
+      }
+      return false;
+  }
+}
+
+// Vector lanes (lane_vec_width: four lanes per row where R allows) when the
+// views' runs are not short, every column block has a kernel and B is aligned
+// to the lane width, else one lane per column.
 template <int N, typename BT>
 void launch_views_typed(const Tensor* tn, const BT* B, int R, float* C, hipStream_t s) {
-  constexpr int V = vec_cols<BT>();
-  if (R % V == 0 && (reinterpret_cast<uintptr_t>(B) & 15) == 0) {
+  bool vec = !tn->short_runs;
+  for (int c0 = 0; c0 < R && vec; c0 += 64) {
+    const int w = std::min(64, R - c0);
+    const int V = lane_vec_width(w, R, sizeof(BT));
+    const int lanes = V ? (w + V - 1) / V : 0;
+    vec = V != 0 && lanes <= (V == 4 ? 16 : 8) &&
+          (reinterpret_cast<uintptr_t>(B) % (static_cast<size_t>(V) * sizeof(BT))) == 0;
+  }
+  if (vec) {
     const ViewSet vs = view_set<N, BT>(tn, kTileVec);
     if (vs.block0[N] == 0) return;
     for (int c0 = 0; c0 < R; c0 += 64) {
       const int w = std::min(64, R - c0);  // a multiple of V
-      int lanes = 1;
-      while (lanes * V < w) lanes *= 2;
-      switch (lanes) {
-        case 1: launch_vec_cols<N, BT, 1>(vs, B, R, C, c0, w, s); break;
-        case 2: launch_vec_cols<N, BT, 2>(vs, B, R, C, c0, w, s); break;
-        case 4: launch_vec_cols<N, BT, 4>(vs, B, R, C, c0, w, s); break;
-        case 8: launch_vec_cols<N, BT, 8>(vs, B, R, C, c0, w, s); break;
+      switch (lane_vec_width(w, R, sizeof(BT))) {
+        case 2: launch_vec_block<N, BT, 2>(vs, B, R, C, c0, w, s); break;
+        case 4: launch_vec_block<N, BT, 4>(vs, B, R, C, c0, w, s); break;
         default:
-          if constexpr (V == 4) launch_vec_cols<N, BT, 16>(vs, B, R, C, c0, w, s);
+          if constexpr (sizeof(BT) == 2) launch_vec_block<N, BT, 8>(vs, B, R, C, c0, w, s);
           break;
       }
     }

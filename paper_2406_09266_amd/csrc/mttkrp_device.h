@@ -239,37 +239,61 @@ __device__ __forceinline__ void mttkrp_view_tile_slot(int t, int e0, int e1, con
   }
 }
 
-// ---- 16-byte lanes ----------------------------------------------------------
+// ---- vector lanes -------------------------------------------------------------
 // The view kernels above give every output column its own lane, so a lane
 // loads 2 (BF16) or 4 (FP32) bytes of a factor row and a wave instruction
 // covers only 64/L rows: at R = 32 the kernels issue a load instruction for
 // every two rows, and their time goes to issuing loads, not to moving bytes.
-// Here each lane loads 16 bytes of a row (V = 8 BF16 or 4 FP32 columns), so a
-// group of Lg = R/V lanes covers a row and a wave instruction covers 64/Lg
-// rows. Requires R to be a multiple of V (rows stay 16-byte aligned).
+// Here each lane loads V consecutive columns of a row (4 to 16 bytes), so a
+// group of Lg = R/V lanes covers a row. V is chosen so that a row takes four
+// lanes where it can (lane_vec_width): with fewer lanes per row each lane
+// carries more columns and an iteration spans more entries, and measured
+// kernels ran up to 3x slower with one or two lanes per row. Requires R to be
+// a multiple of V and B aligned to V elements (rows stay aligned).
 
 // entries in flight per lane group (a group already covers a whole row)
 constexpr int kUnrollVec = 2;
 
-template <typename BT>
-constexpr int vec_cols() {
-  return 16 / static_cast<int>(sizeof(BT));
+// Words (4 bytes) per lane for V elements of BT.
+template <typename BT, int V>
+constexpr int vec_words() {
+  return V * static_cast<int>(sizeof(BT)) / 4;
 }
 
-template <typename BT>
-__device__ __forceinline__ void unpack_vec(const uint4& u, float (&out)[vec_cols<BT>()]) {
-  if constexpr (sizeof(BT) == 2) {
-    const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+// Loads V elements of BT at p (aligned to their size) as raw words.
+template <typename BT, int V>
+__device__ __forceinline__ void load_vec_words(const BT* p, uint32_t (&w)[vec_words<BT, V>()]) {
+  constexpr int W = vec_words<BT, V>();
+  if constexpr (W == 1) {
+    w[0] = *reinterpret_cast<const uint32_t*>(p);
+  } else if constexpr (W == 2) {
+    const uint2 t = *reinterpret_cast<const uint2*>(p);
+    w[0] = t.x;
+    w[1] = t.y;
+  } else {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int k = 0; k < W / 4; ++k) {
+      const uint4 t = reinterpret_cast<const uint4*>(p)[k];
+      w[4 * k] = t.x;
+      w[4 * k + 1] = t.y;
+      w[4 * k + 2] = t.z;
+      w[4 * k + 3] = t.w;
+    }
+  }
+}
+
+// Raw words -> V FP32 values (BF16: the 16 bits become the top half).
+template <typename BT, int V>
+__device__ __forceinline__ void unpack_vec(const uint32_t (&w)[vec_words<BT, V>()], float (&out)[V]) {
+  if constexpr (sizeof(BT) == 2) {
+#pragma unroll
+    for (int q = 0; q < V / 2; ++q) {
       out[2 * q] = __uint_as_float(w[q] << 16);              // element 2q (low half)
       out[2 * q + 1] = __uint_as_float(w[q] & 0xffff0000u);  // element 2q+1 (high half)
     }
   } else {
-    out[0] = __uint_as_float(u.x);
-    out[1] = __uint_as_float(u.y);
-    out[2] = __uint_as_float(u.z);
-    out[3] = __uint_as_float(u.w);
+#pragma unroll
+    for (int q = 0; q < V; ++q) out[q] = __uint_as_float(w[q]);
   }
 }
 
@@ -306,13 +330,13 @@ __device__ __forceinline__ void emit_row_spread(float* __restrict__ C, int ldc, 
 // groups and written once, the entries of the iteration's last row start the
 // next sum, and rows strictly between (runs shorter than an iteration) are
 // written lane by lane.
-template <int N, typename BT, int Lg, int T>
+template <int N, typename BT, int V, int Lg, int T>
 __device__ __forceinline__ void mttkrp_view_range_vec(int e0, int e1, const IdxPtrs& ip,
                                                       const float* __restrict__ val,
                                                       const BT* __restrict__ B, int ldb,
                                                       float* __restrict__ C, int ldc, int col0,
                                                       int ncols) {
-  constexpr int V = vec_cols<BT>();
+  constexpr int W = vec_words<BT, V>();
   constexpr int G = kWave / Lg;
   if (e0 >= e1) return;
   const int lane = threadIdx.x & (kWave - 1);
@@ -336,15 +360,18 @@ __device__ __forceinline__ void mttkrp_view_range_vec(int e0, int e1, const IdxP
       for (int s = 0; s < N; ++s) c[u][s] = ok[u] ? ip.p[s][e] : 0;
       v[u] = ok[u] ? val[e] : 0.0f;
     }
-    uint4 raw[kUnrollVec][N];
+    uint32_t raw[kUnrollVec][N][W];
 #pragma unroll
     for (int u = 0; u < kUnrollVec; ++u)
 #pragma unroll
       for (int s = 0; s < N; ++s) {
         if (s == T) continue;
-        raw[u][s] = (ok[u] && lane_cols)
-                        ? *reinterpret_cast<const uint4*>(B + static_cast<int64_t>(c[u][s]) * ldb + col)
-                        : make_uint4(0u, 0u, 0u, 0u);
+        if (ok[u] && lane_cols) {
+          load_vec_words<BT, V>(B + static_cast<int64_t>(c[u][s]) * ldb + col, raw[u][s]);
+        } else {
+#pragma unroll
+          for (int k = 0; k < W; ++k) raw[u][s][k] = 0u;
+        }
       }
     const int last = out_idx[min(e1, base + G * kUnrollVec) - 1];  // uniform
     float p[kUnrollVec][V];
@@ -357,7 +384,7 @@ __device__ __forceinline__ void mttkrp_view_range_vec(int e0, int e1, const IdxP
       for (int s = 0; s < N; ++s) {
         if (s == T) continue;
         float b[V];
-        unpack_vec<BT>(raw[u][s], b);
+        unpack_vec<BT, V>(raw[u][s], b);
 #pragma unroll
         for (int j = 0; j < V; ++j) p[u][j] *= b[j];
       }
@@ -400,8 +427,8 @@ __device__ __forceinline__ void mttkrp_view_range_vec(int e0, int e1, const IdxP
   emit_row_spread<V, Lg>(C, ldc, cur, col0, ncols, acc);
 }
 
-// Runs view slot t (a value uniform across the wave) with 16-byte lanes.
-template <int N, typename BT, int Lg>
+// Runs view slot t (a value uniform across the wave) with vector lanes.
+template <int N, typename BT, int V, int Lg>
 __device__ __forceinline__ void mttkrp_view_range_vec_slot(int t, int e0, int e1,
                                                            const IdxPtrs& idx,
                                                            const float* __restrict__ val,
@@ -409,16 +436,16 @@ __device__ __forceinline__ void mttkrp_view_range_vec_slot(int t, int e0, int e1
                                                            float* __restrict__ C, int ldc,
                                                            int col0, int ncols) {
   switch (t) {
-    case 0: mttkrp_view_range_vec<N, BT, Lg, 0>(e0, e1, idx, val, B, ldb, C, ldc, col0, ncols); break;
-    case 1: mttkrp_view_range_vec<N, BT, Lg, 1>(e0, e1, idx, val, B, ldb, C, ldc, col0, ncols); break;
-    case 2: mttkrp_view_range_vec<N, BT, Lg, 2>(e0, e1, idx, val, B, ldb, C, ldc, col0, ncols); break;
+    case 0: mttkrp_view_range_vec<N, BT, V, Lg, 0>(e0, e1, idx, val, B, ldb, C, ldc, col0, ncols); break;
+    case 1: mttkrp_view_range_vec<N, BT, V, Lg, 1>(e0, e1, idx, val, B, ldb, C, ldc, col0, ncols); break;
+    case 2: mttkrp_view_range_vec<N, BT, V, Lg, 2>(e0, e1, idx, val, B, ldb, C, ldc, col0, ncols); break;
     case 3:
       if constexpr (N > 3)
-        mttkrp_view_range_vec<N, BT, Lg, 3>(e0, e1, idx, val, B, ldb, C, ldc, col0, ncols);
+        mttkrp_view_range_vec<N, BT, V, Lg, 3>(e0, e1, idx, val, B, ldb, C, ldc, col0, ncols);
       break;
     default:
       if constexpr (N > 4)
-        mttkrp_view_range_vec<N, BT, Lg, 4>(e0, e1, idx, val, B, ldb, C, ldc, col0, ncols);
+        mttkrp_view_range_vec<N, BT, V, Lg, 4>(e0, e1, idx, val, B, ldb, C, ldc, col0, ncols);
       break;
   }
 }

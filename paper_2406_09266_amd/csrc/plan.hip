@@ -337,6 +337,7 @@ int tensor_create_coo(int order, int64_t I, int64_t nnz, const int32_t* const* i
   t->order = order;
   t->dim = I;
   t->nnz = nnz;
+  t->short_runs = nnz < kShortRun * I;
   const int nz = static_cast<int>(nnz);
   const int32_t* ip[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   for (int q = 0; q < order; ++q) ip[q] = idx[q];

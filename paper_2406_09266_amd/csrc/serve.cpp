@@ -194,7 +194,8 @@ class GpuExecutor {
           for (size_t k = 0; k < shares.size() && !rc; ++k) {
             const Share& sh = shares[k];
             if (kind_of(sh.t) != g) continue;
-            if (g > 0 && step_variant(sh.req->dtype, sh.req->R, sh.req->in) != v) continue;
+            if (g > 0 && step_variant(sh.req->dtype, sh.req->R, sh.req->in, sh.t->short_runs) != v)
+              continue;
             if (g == 0 && v != 0) continue;
             StepReq& q = a.req[a.nreq++];
             q.t = sh.t->d_serve;

@@ -59,12 +59,13 @@ __device__ __forceinline__ int find_req(const StepArgs& a, int i) {
 
 // One MTTKRP item is a range of a few tiles of one view; the waves of the
 // workgroup take every fourth tile (one lane per column) or a quarter of the
-// range each (16-byte lanes, which sum runs across the wave).
+// range each (vector lanes, which sum runs across the wave).
 template <int N, typename BT, int L>
 __device__ __forceinline__ void view_range_vec(const ServeTensor* t, const ServeUnit& u,
                                                const StepReq& q) {
-  constexpr int V = vec_cols<BT>();
-  constexpr int Lg = (L / V) < 1 ? 1 : (L / V);  // lanes per row at R <= L
+  constexpr int V = lane_vec_width(L, L, sizeof(BT));  // step_variant checked R % V
+  static_assert(V > 0, "vector lanes need an even lane class");
+  constexpr int Lg = L / V;  // lanes per row at R <= L
   IdxPtrs ip{};
 #pragma unroll
   for (int s = 0; s < N; ++s) ip.p[s] = uni_ptr(static_cast<const int32_t*>(t->p[u.a][s]));
@@ -73,7 +74,7 @@ __device__ __forceinline__ void view_range_vec(const ServeTensor* t, const Serve
   const int w = threadIdx.x / kWave, nw = blockDim.x / kWave;
   const int per = (u.c - u.b + nw - 1) / nw;
   const int e0 = min(u.c, u.b + w * per), e1 = min(u.c, e0 + per);
-  mttkrp_view_range_vec_slot<N, BT, Lg>(u.a, e0, e1, ip, val, B, q.R, q.out, q.R, 0, q.R);
+  mttkrp_view_range_vec_slot<N, BT, V, Lg>(u.a, e0, e1, ip, val, B, q.R, q.out, q.R, 0, q.R);
 }
 
 template <int N, typename BT, int L>

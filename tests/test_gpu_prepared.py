@@ -113,14 +113,35 @@ def test_prepared_mttkrp(order, dim, nnz, R, bdtype, algo):
 
 
 @pytest.mark.parametrize("order,dim,nnz", [(3, 400, 30011), (4, 150, 20021), (5, 70, 12007)])
-@pytest.mark.parametrize("R,bdtype", [(8, "bf16"), (24, "bf16"), (64, "bf16"), (72, "bf16"),
-                                      (136, "bf16"), (4, "f32"), (12, "f32"), (64, "f32")])
+@pytest.mark.parametrize("R,bdtype", [(6, "bf16"), (8, "bf16"), (16, "bf16"), (24, "bf16"),
+                                      (64, "bf16"), (72, "bf16"), (136, "bf16"), (2, "f32"),
+                                      (4, "f32"), (12, "f32"), (32, "f32"), (64, "f32")])
 def test_prepared_mttkrp_vector_lanes(order, dim, nnz, R, bdtype):
-    """Slot views with 16-byte lanes (R a multiple of 8 BF16 or 4 FP32
-    columns): one to sixteen lanes per row, idle lanes when R is not a power
-    of two, and 64-column blocks with a ragged last block."""
+    """Slot views with vector lanes (2, 4 or 8 columns per lane, R even, runs
+    of 75 to 171 entries per index): one to sixteen lanes per row, idle lanes
+    when R/V is not a power of two, and 64-column blocks with a ragged last
+    block of another lane width."""
     t = synth.sym_coo(order, dim, nnz, repeat_frac=0.2, seed=3000 + order * 13 + R)
     B = synth.dense_uniform((dim, R), seed=R + 7)
+    T = systec.Tensor.from_coo([dev(a) for a in t["idx"]], dev(t["val"].astype(np.float32)), dim)
+    Bd = dev(B.astype(np.float32))
+    Bref = f32(B)
+    if bdtype == "bf16":
+        Bd = systec.quantize_bf16(Bd)
+        Bref = oracle.round_bf16(B.astype(np.float32))
+    C = T.mttkrp(Bd, algo="views").cpu().numpy()
+    want, _ = oracle.mttkrp(order, dim, t["idx"].T, f32(t["val"]), Bref)
+    assert rel_err(C, want) <= TOL32
+    T.close()
+
+
+@pytest.mark.parametrize("order,dim,nnz", [(3, 20000, 30011), (4, 5000, 20021)])
+@pytest.mark.parametrize("R,bdtype", [(8, "bf16"), (32, "bf16"), (16, "f32")])
+def test_prepared_mttkrp_short_runs(order, dim, nnz, R, bdtype):
+    """Fewer than 64 stored entries per index (runs of one to four entries
+    per output row): the views take the lane-per-column kernel."""
+    t = synth.sym_coo(order, dim, nnz, repeat_frac=0.05, seed=4000 + order + R)
+    B = synth.dense_uniform((dim, R), seed=R + 11)
     T = systec.Tensor.from_coo([dev(a) for a in t["idx"]], dev(t["val"].astype(np.float32)), dim)
     Bd = dev(B.astype(np.float32))
     Bref = f32(B)
