@@ -116,10 +116,10 @@ struct Tensor {
   // tensor
   int64_t vnnz[5] = {0, 0, 0, 0, 0};
   // Fewer than kShortRun stored entries per index on average: the views' runs
-  // of equal output rows are short, and the view kernels take one lane per
-  // column (each entry one contiguous row update) instead of vector lanes
-  // (one update per lane column for every entry of a run shorter than an
-  // iteration).
+  // of equal output rows are short. Above 16 columns the view kernels then
+  // take one lane per column (each entry one contiguous row update), which
+  // measured faster there than the vector lanes' per-iteration sums of short
+  // rows (use_vector_lanes).
   bool short_runs = false;
   int32_t* vidx[5][5] = {};
   float* vval[5] = {};
@@ -188,8 +188,8 @@ constexpr int kServeLds = kPanelRows * 4;  // bytes: the row sums of one panel
 int launch_serve_prologue(const ZeroArgs& z, hipStream_t s);
 // Step kernel variants: kind 0 is SSYMV (one variant); kinds 3, 4, 5 are
 // MTTKRP of that order, variant = 8 * (input is BF16) + 4 * (vector lanes:
-// the operand's runs are not short, R is a multiple of the class's lane width
-// and the input is aligned to it) + lane class (R <= 8, 16, 32, 64).
+// use_vector_lanes, R a multiple of the class's lane width and the input
+// aligned to it) + lane class (R <= 8, 16, 32, 64).
 constexpr int kStepVariants = 16;
 // Lane width (columns per lane) of the MTTKRP vector-lane kernels for a block
 // of `cols` columns of a factor with R columns of `elem_bytes`-byte elements:
@@ -201,12 +201,14 @@ constexpr int lane_vec_width(int cols, int64_t R, int elem_bytes) {
     if (v * elem_bytes <= 16 && R % v == 0 && (v * 4 <= cols || v == 2)) return v;
   return 0;
 }
+// Whether the view kernels use vector lanes for R columns of a tensor.
+inline bool use_vector_lanes(bool short_runs, int64_t R) { return !(short_runs && R > 16); }
 inline int step_variant(int dtype, int64_t R, const void* in, bool short_runs) {
   const int lane_class = R <= 8 ? 0 : R <= 16 ? 1 : R <= 32 ? 2 : 3;
   const int esize = dtype == SYSTEC_BF16 ? 2 : 4;
   const int L = 8 << lane_class;
   const int V = lane_vec_width(L, L, esize);  // the lane width of the class's kernel
-  const bool vec_lanes = !short_runs && V != 0 && R % V == 0 &&
+  const bool vec_lanes = use_vector_lanes(short_runs, R) && V != 0 && R % V == 0 &&
                          reinterpret_cast<uintptr_t>(in) % static_cast<uintptr_t>(V * esize) == 0;
   return (dtype == SYSTEC_BF16 ? 8 : 0) + (vec_lanes ? 4 : 0) + lane_class;
 }

@@ -238,12 +238,12 @@ bool launch_vec_block(const ViewSet& vs, const BT* B, int R, float* C, int c0, i
   }
 }
 
-// Vector lanes (lane_vec_width: four lanes per row where R allows) when the
-// views' runs are not short, every column block has a kernel and B is aligned
+// Vector lanes (lane_vec_width: four lanes per row where R allows) when
+// use_vector_lanes allows, every column block has a kernel and B is aligned
 // to the lane width, else one lane per column.
 template <int N, typename BT>
 void launch_views_typed(const Tensor* tn, const BT* B, int R, float* C, hipStream_t s) {
-  bool vec = !tn->short_runs;
+  bool vec = use_vector_lanes(tn->short_runs, R);
   for (int c0 = 0; c0 < R && vec; c0 += 64) {
     const int w = std::min(64, R - c0);
     const int V = lane_vec_width(w, R, sizeof(BT));

@@ -323,13 +323,57 @@ __device__ __forceinline__ void emit_row_spread(float* __restrict__ C, int ldc, 
     atomic_add_noret(C + static_cast<int64_t>(row) * ldc + col0 + lane, x);
 }
 
+// Rows of one unroll slot that lie strictly between the iteration's first
+// and last rows (runs shorter than an iteration). The slot's entries are
+// sorted, so a row's entries sit in consecutive lane groups: a segmented sum
+// across the groups leaves each row's total in its last group, which writes
+// it with one atomic per column (spread as in emit_row_spread). key < 0 marks
+// entries of no such row; v holds the lane's V columns of its entry.
+template <int V, int Lg>
+__device__ __forceinline__ void emit_short_rows(float* __restrict__ C, int ldc, int col0,
+                                                int ncols, int key, float (&v)[V]) {
+  constexpr int G = kWave / Lg;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int g = lane / Lg;
+  // (every shuffle runs in all lanes: a lane that reads from a lane left out
+  // of a divergent shuffle gets 0, not that lane's value)
+#pragma unroll
+  for (int d = 1; d < G; d *= 2) {
+    const int earlier = __shfl_up(key, d * Lg);
+    const bool same = g >= d && earlier == key;
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      const float t = __shfl_up(v[j], d * Lg);
+      v[j] += same ? t : 0.0f;
+    }
+  }
+  const int next = __shfl_down(key, Lg);
+  const bool ends = key >= 0 && (g == G - 1 || next != key);
+  uint64_t heads = __ballot(ends && lane % Lg == 0);  // the first lane of each ending group
+  const int j = lane % V;
+  while (heads != 0) {
+    const int first = __ffsll(static_cast<unsigned long long>(heads)) - 1;
+    heads &= heads - 1;
+    const int row = __shfl(key, first);
+    const int src = first + lane / V;  // the lane holding column `lane` (lanes < V * Lg)
+    float x = 0.0f;
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      const float t = __shfl(v[q], src);
+      x = (j == q) ? t : x;
+    }
+    if (lane < ncols && lane < V * Lg)
+      atomic_add_noret(C + static_cast<int64_t>(row) * ldc + col0 + lane, x);
+  }
+}
+
 // A wave runs entries [e0, e1) of view T (sorted by c_T). Lane group g takes
 // entry base + u*G + g of each iteration, so index loads are coalesced. Each
 // lane sums the entries of the wave's current output row `cur`; when an
 // iteration reaches a later row, the sums for `cur` are added across the
 // groups and written once, the entries of the iteration's last row start the
 // next sum, and rows strictly between (runs shorter than an iteration) are
-// written lane by lane.
+// summed across the groups and written once per row (emit_short_rows).
 template <int N, typename BT, int V, int Lg, int T>
 __device__ __forceinline__ void mttkrp_view_range_vec(int e0, int e1, const IdxPtrs& ip,
                                                       const float* __restrict__ val,
@@ -398,18 +442,20 @@ __device__ __forceinline__ void mttkrp_view_range_vec(int e0, int e1, const IdxP
     }
 #pragma unroll
     for (int u = 0; u < kUnrollVec; ++u) {
-      if (!ok[u]) continue;
       const int row = c[u][T];
-      if (row == cur) {
+      const bool between = ok[u] && row != cur && row != last;
+      if (ok[u] && row == cur) {
 #pragma unroll
         for (int j = 0; j < V; ++j) acc[j] += p[u][j];
-      } else if (row == last) {
+      } else if (ok[u] && row == last) {
 #pragma unroll
         for (int j = 0; j < V; ++j) nxt[j] += p[u][j];
-      } else if (lane_cols) {  // a run shorter than an iteration
-        float* out = C + static_cast<int64_t>(row) * ldc + col;
+      }
+      if (__ballot(between) != 0) {  // runs shorter than an iteration
+        float v[V];
 #pragma unroll
-        for (int j = 0; j < V; ++j) atomic_add_noret(out + j, p[u][j]);
+        for (int j = 0; j < V; ++j) v[j] = between ? p[u][j] : 0.0f;
+        emit_short_rows<V, Lg>(C, ldc, col0, ncols, between ? row : -1, v);
       }
     }
 #pragma unroll

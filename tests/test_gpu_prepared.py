@@ -136,10 +136,11 @@ def test_prepared_mttkrp_vector_lanes(order, dim, nnz, R, bdtype):
 
 
 @pytest.mark.parametrize("order,dim,nnz", [(3, 20000, 30011), (4, 5000, 20021)])
-@pytest.mark.parametrize("R,bdtype", [(8, "bf16"), (32, "bf16"), (16, "f32")])
+@pytest.mark.parametrize("R,bdtype", [(8, "bf16"), (32, "bf16"), (16, "f32"), (40, "f32")])
 def test_prepared_mttkrp_short_runs(order, dim, nnz, R, bdtype):
     """Fewer than 64 stored entries per index (runs of one to four entries
-    per output row): the views take the lane-per-column kernel."""
+    per output row): vector lanes summing the short rows of an iteration
+    across lane groups up to 16 columns, one lane per column above."""
     t = synth.sym_coo(order, dim, nnz, repeat_frac=0.05, seed=4000 + order + R)
     B = synth.dense_uniform((dim, R), seed=R + 11)
     T = systec.Tensor.from_coo([dev(a) for a in t["idx"]], dev(t["val"].astype(np.float32)), dim)
