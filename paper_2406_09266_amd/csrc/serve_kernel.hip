@@ -96,7 +96,7 @@ __device__ __forceinline__ void view_range(const ServeTensor* t, const ServeUnit
 // tensor order so that each keeps the registers of its own order); the four
 // waves of an MTTKRP workgroup share an item of a few tiles each.
 __global__ __launch_bounds__(kServeBlock) void serve_ssymv_kernel(StepArgs a) {
-  extern __shared__ float s_lds[];
+  extern __shared__ double s_lds[];
   const int i = blockIdx.x;
   const StepReq& r = a.req[find_req(a, i)];
   const ServeTensor* t = r.t;

@@ -240,7 +240,7 @@ __global__ __launch_bounds__(kPanelThreads) void ssymv_panel_kernel(
     const int32_t* __restrict__ chunk_tile_begin, const int32_t* __restrict__ chunk_tile_end,
     const int32_t* __restrict__ pcol, const uint16_t* __restrict__ prow,
     const float* __restrict__ pval, const XT* __restrict__ x, float* __restrict__ y) {
-  extern __shared__ float s_rows[];  // the panel's row sums
+  extern __shared__ double s_rows[];  // the panel's row sums
   const int chunk = blockIdx.x;
   ssymv_panel_chunk<XT>(n, H, chunk_panel[chunk], chunk_tile_begin[chunk], chunk_tile_end[chunk],
                         pcol, prow, pval, x, y, s_rows);
@@ -320,7 +320,7 @@ int launch_ssymv_panel(const Tensor* t, const void* x, systec_dtype xdt, float* 
                        hipStream_t s) {
   int rc = launch_fill_f32(y, t->dim, s);
   if (rc != SYSTEC_OK || t->nchunks == 0) return rc;
-  const size_t lds = static_cast<size_t>(t->panel_rows) * sizeof(float);
+  const size_t lds = static_cast<size_t>(t->panel_rows) * sizeof(double);
   const int n = static_cast<int>(t->dim);
   // more than the default 64 KiB of dynamic LDS
   rc = check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(ssymv_panel_kernel<float>),
