@@ -52,6 +52,9 @@ def parse():
                     help="served_mix: requests running at once")
     ap.add_argument("--max-inflight", type=int, default=0,
                     help="served_mix: steps queued on the device at once (0: the server default)")
+    ap.add_argument("--relabel", default="auto", choices=["auto", "on", "off"],
+                    help="SSYMV: prepare the matrix with its vertices ordered by degree "
+                         "(auto: when the degrees are skewed)")
     ap.add_argument("--served-dtype", default="bf16", choices=["bf16", "f32"],
                     help="served_mix: input dtype of the served requests (the plain form is FP32)")
     ap.add_argument("--min-step-work", type=int, default=0,
@@ -168,13 +171,15 @@ def main():
         b_alg = 4 * (n + 1) + 8 * U + n * sx + 4 * n
         oneshot = lambda: systec.ssymv(rp, col, val, x, out=y)  # noqa: E731
         t_prep = time.perf_counter()
-        A = systec.Tensor.from_csr(rp, col, val)
+        relabel = {"auto": None, "on": True, "off": False}[a.relabel]
+        A = systec.Tensor.from_csr(rp, col, val, relabel=relabel)
         t_prep = time.perf_counter() - t_prep
         prepared = lambda: A.ssymv(x, out=y)  # noqa: E731
         kernel_key = "ssymv_panel" if a.path == "prepared" else "ssymv"
         kernel_src = ("ssymv.hip", "panel_device.h", "wave_ops.h", "plan.hip")
         cfg = {"workload": a.workload, "n": n, "stored_nnz": U, "effective_nnz": eff,
-               "diagonal_nnz": hist[1], "x_storage": a.form, "accumulate": "f32"}
+               "diagonal_nnz": hist[1], "x_storage": a.form, "accumulate": "f32",
+               "vertex_order": a.relabel}
     else:
         order, I = w["order"], w["dim"]
         R = w["B"].shape[1]

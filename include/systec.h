@@ -271,6 +271,20 @@ typedef struct systec_tensor systec_tensor;
 SYSTEC_API int systec_tensor_create_csr(int64_t n, int64_t nnz, const int32_t* rowptr,
                                         const int32_t* col, const float* val,
                                         systec_stream stream, systec_tensor** out);
+/* systec_tensor_create_csr with the vertex order chosen by the caller.
+ * relabel = 1 stores the matrix with its vertices ordered by descending
+ * degree (a symmetric permutation P A P^T, ties in vertex order): the
+ * high-degree vertices then share panels and columns, and the column-side
+ * updates of systec_ssymv_t merge into fewer cache lines; each call then
+ * permutes x in and y out (two gathers of n elements, inside the call, on
+ * its stream, with stream-ordered scratch). relabel = 0 keeps the order
+ * (what systec_tensor_create_csr does); relabel = -1 relabels when the
+ * largest degree exceeds 8 times the mean (power-law graphs). Anything else
+ * is SYSTEC_EINVAL. A relabeled matrix cannot be registered with a server
+ * (SYSTEC_EINVAL). */
+SYSTEC_API int systec_tensor_create_csr_ex(int64_t n, int64_t nnz, const int32_t* rowptr,
+                                           const int32_t* col, const float* val, int relabel,
+                                           systec_stream stream, systec_tensor** out);
 SYSTEC_API int systec_tensor_create_coo(int order, int64_t I, int64_t nnz,
                                         const int32_t* const* idx, const float* val,
                                         systec_stream stream, systec_tensor** out);

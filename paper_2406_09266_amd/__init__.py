@@ -277,13 +277,18 @@ class Tensor:
         self.effective_nnz, self.bytes = eff.value, nbytes.value
 
     @classmethod
-    def from_csr(cls, rowptr, col, val, stream=None):
+    def from_csr(cls, rowptr, col, val, stream=None, relabel=False):
+        """relabel: True stores the matrix with its vertices ordered by degree
+        (each ssymv then permutes x in and y out; faster on power-law
+        graphs), False keeps the order, None lets the library decide from the
+        degree skew. A relabeled matrix cannot be registered with a Server."""
         torch = _torch()
         _dev(rowptr, torch.int32, "rowptr"), _dev(col, torch.int32, "col")
         _dev(val, torch.float32, "val")
         h = ctypes.c_void_p()
-        call("systec_tensor_create_csr", rowptr.numel() - 1, col.numel(), _p(rowptr), _p(col),
-             _p(val), _stream(stream), ctypes.byref(h))
+        code = -1 if relabel is None else (1 if relabel else 0)
+        call("systec_tensor_create_csr_ex", rowptr.numel() - 1, col.numel(), _p(rowptr), _p(col),
+             _p(val), code, _stream(stream), ctypes.byref(h))
         return cls(h)
 
     @classmethod

@@ -46,6 +46,7 @@ SIGNATURES = {
     "systec_canonicalize_coo": [I32, I64, PP, P, PI64],
     "systec_quantize_bf16": [P, P, I64, P],
     "systec_tensor_create_csr": [I64, I64, P, P, P, P, PP],
+    "systec_tensor_create_csr_ex": [I64, I64, P, P, P, I32, P, PP],
     "systec_tensor_create_coo": [I32, I64, I64, PP, P, P, PP],
     "systec_tensor_info": [P, ctypes.POINTER(ctypes.c_int), PI64, PI64, PI64,
                            ctypes.POINTER(ctypes.c_uint64)],

@@ -363,15 +363,23 @@ int systec_quantize_bf16(const float* in, uint16_t* out, int64_t n, systec_strea
 
 int systec_tensor_create_csr(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col,
                              const float* val, systec_stream stream, systec_tensor** out) {
+  return systec_tensor_create_csr_ex(n, nnz, rowptr, col, val, 0, stream, out);
+}
+
+int systec_tensor_create_csr_ex(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col,
+                                const float* val, int relabel, systec_stream stream,
+                                systec_tensor** out) {
   int rc = check_csr_args("systec_tensor_create_csr", n, nnz, rowptr, col, val, rowptr,
                           SYSTEC_F32, out);
   if (rc) return rc;
+  if (relabel < -1 || relabel > 1)
+    return fail(SYSTEC_EINVAL, "systec_tensor_create_csr_ex: relabel must be -1, 0 or 1");
   if ((rc = systec_validate_csr_upper(n, nnz, rowptr, col, stream))) return rc;
   auto s = static_cast<hipStream_t>(stream);
   int64_t full = 0;
   if (nnz > 0 && (rc = expand_csr_size(n, nnz, rowptr, col, &full, s))) return rc;
   Tensor* t = nullptr;
-  if ((rc = tensor_create_csr(n, nnz, rowptr, col, val, kPanelRows, s, &t))) return rc;
+  if ((rc = tensor_create_csr(n, nnz, rowptr, col, val, kPanelRows, relabel, s, &t))) return rc;
   t->effective_nnz = full;
   *out = new systec_tensor{t};
   return SYSTEC_OK;

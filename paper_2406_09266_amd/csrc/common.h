@@ -113,6 +113,11 @@ struct Tensor {
   int32_t* chunk_tile_begin = nullptr;
   int32_t* chunk_tile_end = nullptr;
   std::vector<int32_t> h_chunk_panel, h_chunk_tile_begin, h_chunk_tile_end;  // host copies
+  // vertex relabeling (matrix prepared with its vertices ordered by degree):
+  // the panels hold P A P^T; perm[new] = old, inv[old] = new
+  bool relabeled = false;
+  int32_t* perm = nullptr;
+  int32_t* inv = nullptr;
   // tensor
   int64_t vnnz[5] = {0, 0, 0, 0, 0};
   // Fewer than kShortRun stored entries per index on average: the views' runs
@@ -128,8 +133,11 @@ struct Tensor {
   ServeUnit* d_units = nullptr;
   std::vector<void*> allocations;
 };
+// relabel: 1 orders the vertices by degree, 0 keeps them, -1 decides from the
+// degree skew.
 int tensor_create_csr(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col,
-                      const float* val, int panel_rows, hipStream_t s, Tensor** out);
+                      const float* val, int panel_rows, int relabel, hipStream_t s,
+                      Tensor** out);
 int tensor_create_coo(int order, int64_t I, int64_t nnz, const int32_t* const* idx,
                       const float* val, hipStream_t s, Tensor** out);
 void tensor_free(Tensor* t);

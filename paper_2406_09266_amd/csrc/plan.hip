@@ -48,6 +48,60 @@ __global__ void entry_rows_kernel(int n, int nnz, const int32_t* __restrict__ ro
   }
 }
 
+// ---- vertex relabeling by degree ----
+// deg[v]: stored entries in row v plus off-diagonal stored entries in column
+// v (the vertex's degree in the symmetric matrix).
+__global__ void degree_kernel(int nnz, const int32_t* __restrict__ rows,
+                              const int32_t* __restrict__ col, int32_t* __restrict__ deg) {
+  const int stride = gridDim.x * blockDim.x;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += stride) {
+    atomicAdd(deg + rows[e], 1);
+    if (col[e] != rows[e]) atomicAdd(deg + col[e], 1);
+  }
+}
+
+// Largest degree (one atomic per workgroup) and the sort keys: descending
+// degree, ties in vertex order (the radix sort is stable).
+__global__ void degree_keys_kernel(int n, const int32_t* __restrict__ deg,
+                                   uint32_t* __restrict__ keys, uint32_t* __restrict__ ids,
+                                   int* __restrict__ max_deg) {
+  __shared__ int s_max;
+  if (threadIdx.x == 0) s_max = 0;
+  __syncthreads();
+  int m = 0;
+  const int stride = gridDim.x * blockDim.x;
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+    const int d = deg[v];
+    m = max(m, d);
+    keys[v] = 0xffffffffu - static_cast<uint32_t>(d);
+    ids[v] = static_cast<uint32_t>(v);
+  }
+  atomicMax(&s_max, m);
+  __syncthreads();
+  if (threadIdx.x == 0) atomicMax(max_deg, s_max);
+}
+
+// inv[perm[i]] = i
+__global__ void invert_perm_kernel(int n, const uint32_t* __restrict__ perm,
+                                   int32_t* __restrict__ inv) {
+  const int stride = gridDim.x * blockDim.x;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    inv[perm[i]] = i;
+}
+
+// The stored entry (r, c), r <= c, in the new labels: (min, max) of
+// (inv[r], inv[c]), so it stays in the upper triangle.
+__global__ void relabel_entries_kernel(int nnz, const int32_t* __restrict__ inv,
+                                       int32_t* __restrict__ rows, const int32_t* __restrict__ col,
+                                       int32_t* __restrict__ col_out) {
+  const int stride = gridDim.x * blockDim.x;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += stride) {
+    const int a = inv[rows[e]], b = inv[col[e]];
+    rows[e] = min(a, b);
+    col_out[e] = max(a, b);
+  }
+}
+
 // sort key of a stored entry: (panel, column, row within panel)
 __global__ void panel_keys_kernel(int nnz, int hbits, const int32_t* __restrict__ rows,
                                   const int32_t* __restrict__ col,
@@ -208,8 +262,59 @@ void tensor_free(Tensor* t) {
   delete t;
 }
 
+// Relabels the vertices by descending degree (relabel > 0 always, < 0 when
+// the largest degree exceeds kRelabelSkew times the mean): a symmetric
+// permutation P A P^T that puts the high-degree vertices together, so that
+// a panel's entries share columns and the column-side updates of the SSYMV
+// merge into fewer cache lines (at R-MAT scale 22, 2.4 M instead of 5.3 M
+// 64-byte lines). rows is rewritten in place; *keycol points to the
+// relabeled columns (scratch owned by sc). Stores perm (new -> old) and inv
+// (old -> new) on the tensor.
+constexpr int kRelabelSkew = 8;
+
+static int relabel_by_degree(Tensor* t, int n, int nnz, int32_t* rows, const int32_t* col,
+                             int relabel, Scratch& sc, hipStream_t s, const int32_t** keycol) {
+  int32_t *deg = nullptr, *col2 = nullptr;
+  uint32_t *kin = nullptr, *kout = nullptr, *vin = nullptr;
+  int* d_max = nullptr;
+  int rc = sc.alloc(&deg, n);
+  if (!rc) rc = sc.alloc(&kin, n);
+  if (!rc) rc = sc.alloc(&kout, n);
+  if (!rc) rc = sc.alloc(&vin, n);
+  if (!rc) rc = sc.alloc(&d_max, 1);
+  if (!rc) rc = check_hip(hipMemsetAsync(deg, 0, n * sizeof(int32_t), s), "hipMemsetAsync");
+  if (!rc) rc = check_hip(hipMemsetAsync(d_max, 0, sizeof(int), s), "hipMemsetAsync");
+  if (rc) return rc;
+  degree_kernel<<<grid_for(nnz, 256), 256, 0, s>>>(nnz, rows, col, deg);
+  degree_keys_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, deg, kin, vin, d_max);
+  if ((rc = check_launch("degree kernels"))) return rc;
+  if (relabel < 0) {
+    int h_max = 0;
+    rc = check_hip(hipMemcpyAsync(&h_max, d_max, sizeof(int), hipMemcpyDeviceToHost, s),
+                   "hipMemcpyAsync");
+    if (!rc) rc = check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+    if (rc) return rc;
+    // the mean degree is at most 2 nnz / n
+    if (static_cast<int64_t>(h_max) * n <= static_cast<int64_t>(kRelabelSkew) * 2 * nnz)
+      return SYSTEC_OK;
+  }
+  if ((rc = tensor_alloc(t, &t->perm, n))) return rc;
+  if ((rc = tensor_alloc(t, &t->inv, n))) return rc;
+  if ((rc = sc.alloc(&col2, nnz))) return rc;
+  if ((rc = radix_sort_pairs(kin, kout, vin, reinterpret_cast<uint32_t*>(t->perm), n, 32, s)))
+    return rc;
+  invert_perm_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, reinterpret_cast<const uint32_t*>(t->perm),
+                                                     t->inv);
+  relabel_entries_kernel<<<grid_for(nnz, 256), 256, 0, s>>>(nnz, t->inv, rows, col, col2);
+  if ((rc = check_launch("relabel kernels"))) return rc;
+  t->relabeled = true;
+  *keycol = col2;
+  return SYSTEC_OK;
+}
+
 int tensor_create_csr(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col,
-                      const float* val, int panel_rows, hipStream_t s, Tensor** out) {
+                      const float* val, int panel_rows, int relabel, hipStream_t s,
+                      Tensor** out) {
   const int hbits = bits_for(panel_rows);
   const int H = 1 << hbits;
   auto* t = new Tensor();
@@ -247,8 +352,13 @@ int tensor_create_csr(int64_t n, int64_t nnz, const int32_t* rowptr, const int32
   }
   if (nnz > 0) {
     entry_rows_kernel<<<grid_for(nnz, 256), 256, 0, s>>>(ni, nz, rowptr, rows);
-    panel_keys_kernel<<<grid_for(nnz, 256), 256, 0, s>>>(nz, hbits, rows, col, kin, vin);
-    rc = check_launch("panel key kernels");
+    rc = check_launch("entry row kernel");
+    const int32_t* keycol = col;
+    if (!rc && relabel != 0) rc = relabel_by_degree(t, ni, nz, rows, col, relabel, sc, s, &keycol);
+    if (!rc) {
+      panel_keys_kernel<<<grid_for(nnz, 256), 256, 0, s>>>(nz, hbits, rows, keycol, kin, vin);
+      rc = check_launch("panel key kernels");
+    }
     if (!rc) rc = radix_sort_pairs(kin, kout, vin, vout, nz, 31 + hbits + bits_for(P + 1), s);
     if (!rc) {
       panel_starts_kernel<<<grid_for(nz, 256), 256, 0, s>>>(nz, hbits, P, kout, d_start);

@@ -317,6 +317,10 @@ int systec_serve_create(const systec_serve_config* cfg, systec_server** out) {
 int systec_serve_register(systec_server* s, systec_tensor* t, int64_t* tensor_id) {
   if (!s || !t || !t->impl || !tensor_id)
     return serve_fail(SYSTEC_EINVAL, "systec_serve_register: NULL argument");
+  if (t->impl->relabeled)
+    return serve_fail(SYSTEC_EINVAL,
+                      "systec_serve_register: the matrix was prepared with its vertices relabeled; "
+                      "create it with systec_tensor_create_csr_ex(..., relabel = 0, ...) to serve it");
   auto e = std::make_shared<serve::TensorEntry>();
   std::string err;
   if (!t->impl->d_serve) {

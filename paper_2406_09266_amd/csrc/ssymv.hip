@@ -246,6 +246,21 @@ __global__ __launch_bounds__(kPanelThreads) void ssymv_panel_kernel(
                         pcol, prow, pval, x, y, s_rows);
 }
 
+// xp[i] = x[perm[i]] (the input in the prepared matrix's vertex order)
+template <typename XT>
+__global__ void permute_in_kernel(int n, const int32_t* __restrict__ perm, const XT* __restrict__ x,
+                                  XT* __restrict__ xp) {
+  const int stride = gridDim.x * blockDim.x;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) xp[i] = x[perm[i]];
+}
+
+// y[j] = yp[inv[j]] (the output back in the caller's vertex order)
+__global__ void permute_out_kernel(int n, const int32_t* __restrict__ inv,
+                                   const float* __restrict__ yp, float* __restrict__ y) {
+  const int stride = gridDim.x * blockDim.x;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride) y[j] = yp[inv[j]];
+}
+
 __global__ void fill_f32_kernel(float* __restrict__ p, int64_t n) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
@@ -316,8 +331,10 @@ int launch_syprd(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* c
   return rc != SYSTEC_OK ? rc : rc2;
 }
 
-int launch_ssymv_panel(const Tensor* t, const void* x, systec_dtype xdt, float* y,
-                       hipStream_t s) {
+namespace {
+
+// The panel kernel over a prepared matrix in its own vertex order.
+int panel_call(const Tensor* t, const void* x, systec_dtype xdt, float* y, hipStream_t s) {
   int rc = launch_fill_f32(y, t->dim, s);
   if (rc != SYSTEC_OK || t->nchunks == 0) return rc;
   const size_t lds = static_cast<size_t>(t->panel_rows) * sizeof(double);
@@ -343,6 +360,44 @@ int launch_ssymv_panel(const Tensor* t, const void* x, systec_dtype xdt, float* 
         n, t->panel_rows, t->chunk_panel, t->chunk_tile_begin, t->chunk_tile_end, t->pcol,
         t->prow, t->pval, static_cast<const uint16_t*>(x), y);
   return check_launch("ssymv panel kernel");
+}
+
+}  // namespace
+
+int launch_ssymv_panel(const Tensor* t, const void* x, systec_dtype xdt, float* y,
+                       hipStream_t s) {
+  if (!t->relabeled) return panel_call(t, x, xdt, y, s);
+  // relabeled matrix: x in the prepared order, the panels, y back in the
+  // caller's order (stream-ordered scratch)
+  const int n = static_cast<int>(t->dim);
+  if (n == 0) return SYSTEC_OK;
+  const size_t xb = static_cast<size_t>(n) * (xdt == SYSTEC_F32 ? 4 : 2);
+  void* xp = nullptr;
+  float* yp = nullptr;
+  int rc = check_hip(hipMallocAsync(&xp, xb, s), "hipMallocAsync(permuted x)");
+  if (rc) return rc;
+  rc = check_hip(hipMallocAsync(reinterpret_cast<void**>(&yp), static_cast<size_t>(n) * sizeof(float), s),
+                 "hipMallocAsync(permuted y)");
+  if (rc) {
+    (void)hipFreeAsync(xp, s);
+    return rc;
+  }
+  const int grid = static_cast<int>(std::min<int64_t>((n + 255) / 256, 8192));
+  if (xdt == SYSTEC_F32)
+    permute_in_kernel<float><<<grid, 256, 0, s>>>(n, t->perm, static_cast<const float*>(x),
+                                                 static_cast<float*>(xp));
+  else
+    permute_in_kernel<uint16_t><<<grid, 256, 0, s>>>(n, t->perm, static_cast<const uint16_t*>(x),
+                                                    static_cast<uint16_t*>(xp));
+  rc = check_launch("ssymv input permutation");
+  if (!rc) rc = panel_call(t, xp, xdt, yp, s);
+  if (!rc) {
+    permute_out_kernel<<<grid, 256, 0, s>>>(n, t->inv, yp, y);
+    rc = check_launch("ssymv output permutation");
+  }
+  const int rc2 = check_hip(hipFreeAsync(xp, s), "hipFreeAsync");
+  const int rc3 = check_hip(hipFreeAsync(yp, s), "hipFreeAsync");
+  return rc ? rc : (rc2 ? rc2 : rc3);
 }
 
 }  // namespace systec

@@ -57,6 +57,34 @@ def test_prepared_ssymv(case, xdtype):
     A.close()
 
 
+@pytest.mark.parametrize("case", ["small_n2000", "uniform_n40000_ragged_panels", "rmat_scale16",
+                                  "diagonal_only"])
+@pytest.mark.parametrize("relabel", [True, False])
+@pytest.mark.parametrize("xdtype", ["f32", "bf16"])
+def test_prepared_ssymv_vertex_order(case, relabel, xdtype):
+    """The matrix stored with its vertices ordered by degree (x permuted in,
+    y permuted out) or in the caller's order gives the oracle's result."""
+    m = MATRICES[case]()
+    A = systec.Tensor.from_csr(dev(m["rowptr"]), dev(m["col"]), dev(m["val"].astype(np.float32)),
+                               relabel=relabel)
+    x, xref = _x(m, xdtype)
+    y = A.ssymv(x).cpu().numpy()
+    want, counts = oracle.ssymv(m["n"], m["rowptr"], m["col"], f32(m["val"]), xref)
+    assert rel_err(y, want) <= TOL32
+    assert A.effective_nnz == counts["effective_nnz"]
+    A.close()
+
+
+def test_relabeled_matrix_is_not_served():
+    m = synth.ssymv_rmat(scale=12, batch=1 << 15, seed=55)
+    A = systec.Tensor.from_csr(dev(m["rowptr"]), dev(m["col"]), dev(m["val"].astype(np.float32)),
+                               relabel=True)
+    with systec.Server(budget_bytes=1 << 30) as srv:
+        with pytest.raises(systec.SystecError) as e:
+            srv.register(A)
+        assert "relabel" in str(e.value)
+
+
 def test_prepared_ssymv_empty_rows_and_panels():
     import torch
     # rows only in the last panel; earlier panels empty
