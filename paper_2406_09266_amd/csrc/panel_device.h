@@ -17,16 +17,26 @@ namespace dev {
 // entries), so the column-side updates y[j] += a x[i] reduce across the wave
 // by a segmented scan per step, and the segment totals leave in one atomic
 // instruction whose lanes hold consecutive columns (coalesced into few cache
-// lines). A segment running past the step carries into the next step.
-template <typename XT>
+// lines). A segment running past the step carries into the next step; the
+// carry is wave-uniform and moves through scalar registers (readlane), not
+// through LDS.
+// With kStageX the panel's slice of x (H elements) is copied to s_x first and
+// the row-side gathers x[i] read LDS: their rows are scattered over the
+// panel, so from global memory each such wave load touches up to 64 cache
+// lines and the L1 tag lookups, not HBM, set the pace.
+template <typename XT, bool kStageX = false>
 __device__ __forceinline__ void ssymv_panel_chunk(int n, int H, int p, int tb, int te,
                                                   const int32_t* __restrict__ pcol,
                                                   const uint16_t* __restrict__ prow,
                                                   const float* __restrict__ pval,
                                                   const XT* __restrict__ x, float* __restrict__ y,
-                                                  double* s_rows) {
+                                                  double* s_rows, XT* s_x = nullptr) {
   const int r0 = p * H;
   for (int i = threadIdx.x; i < H; i += blockDim.x) s_rows[i] = 0.0;
+  if constexpr (kStageX) {
+    for (int i = threadIdx.x; i < H; i += blockDim.x)
+      s_x[i] = r0 + i < n ? x[r0 + i] : XT(0);
+  }
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1);
   const int w = threadIdx.x / kWave;
@@ -42,17 +52,28 @@ __device__ __forceinline__ void ssymv_panel_chunk(int n, int H, int p, int tb, i
       ro[k] = prow[base + k * kWave];
       a[k] = pval[base + k * kWave];
     }
+    // every gather of the tile is issued before the first update (a gather
+    // behind a branch waits for all earlier memory operations, the atomics
+    // included); padding entries point at a valid diagonal position, so no
+    // gather needs a guard
+    float xc[kV];
+    float xr[kV];
+#pragma unroll
+    for (int k = 0; k < kV; ++k) {
+      xc[k] = load_f32(x, c[k]);
+      xr[k] = kStageX ? load_f32(s_x, ro[k]) : load_f32(x, r0 + ro[k]);
+    }
     int carry_key = -1;
     float carry = 0.0f;
 #pragma unroll
     for (int k = 0; k < kV; ++k) {
       const int r = r0 + ro[k];
       if (a[k] != 0.0f)  // y[i] += a x[j]
-        atomicAdd(s_rows + ro[k], static_cast<double>(a[k] * load_f32(x, c[k])));
-      const float v = (c[k] != r) ? a[k] * load_f32(x, r) : 0.0f;           // y[j] += a x[i]
+        atomicAdd(s_rows + ro[k], static_cast<double>(a[k] * xc[k]));
+      const float v = (c[k] != r) ? a[k] * xr[k] : 0.0f;  // y[j] += a x[i]
       // the previous step's last segment either continues in lane 0 here or
       // is complete and must be written now
-      if (__shfl(c[k], 0) != carry_key) {
+      if (__builtin_amdgcn_readlane(c[k], 0) != carry_key) {
         if (lane == 0 && carry != 0.0f) atomic_add_noret(y + carry_key, carry);
         carry_key = -1;
         carry = 0.0f;
@@ -62,8 +83,8 @@ __device__ __forceinline__ void ssymv_panel_chunk(int n, int H, int p, int tb, i
       const int next_key = __shfl_down(c[k], 1);
       const bool ends = lane != kWave - 1 && next_key != c[k];
       if (ends && seg != 0.0f) atomic_add_noret(y + c[k], seg);
-      carry_key = __shfl(c[k], kWave - 1);
-      carry = __shfl(seg, kWave - 1);
+      carry_key = __builtin_amdgcn_readlane(c[k], kWave - 1);
+      carry = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(seg), kWave - 1));
     }
     if (lane == 0 && carry != 0.0f) atomic_add_noret(y + carry_key, carry);
   }

@@ -27,7 +27,7 @@
 namespace systec {
 namespace {
 
-constexpr int kChunkTiles = 64;  // panel tiles per workgroup work item
+constexpr int kChunkTiles = 96;  // panel tiles per workgroup work item
 
 int grid_for(int64_t n, int block) {
   return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>((n + block - 1) / block, 8192)));

@@ -234,7 +234,9 @@ __global__ __launch_bounds__(1024) void reduce_partials_f64(const float* __restr
   }
 }
 
-template <typename XT>
+// kStageX: the panel's slice of x follows the row sums in LDS (H doubles,
+// then H elements of x).
+template <typename XT, bool kStageX>
 __global__ __launch_bounds__(kPanelThreads) void ssymv_panel_kernel(
     int n, int H, const int32_t* __restrict__ chunk_panel,
     const int32_t* __restrict__ chunk_tile_begin, const int32_t* __restrict__ chunk_tile_end,
@@ -242,16 +244,21 @@ __global__ __launch_bounds__(kPanelThreads) void ssymv_panel_kernel(
     const float* __restrict__ pval, const XT* __restrict__ x, float* __restrict__ y) {
   extern __shared__ double s_rows[];  // the panel's row sums
   const int chunk = blockIdx.x;
-  ssymv_panel_chunk<XT>(n, H, chunk_panel[chunk], chunk_tile_begin[chunk], chunk_tile_end[chunk],
-                        pcol, prow, pval, x, y, s_rows);
+  ssymv_panel_chunk<XT, kStageX>(n, H, chunk_panel[chunk], chunk_tile_begin[chunk],
+                                 chunk_tile_end[chunk], pcol, prow, pval, x, y, s_rows,
+                                 reinterpret_cast<XT*>(s_rows + H));
 }
 
-// xp[i] = x[perm[i]] (the input in the prepared matrix's vertex order)
+// xp[i] = x[perm[i]] (the input in the prepared matrix's vertex order), and
+// yp cleared
 template <typename XT>
 __global__ void permute_in_kernel(int n, const int32_t* __restrict__ perm, const XT* __restrict__ x,
-                                  XT* __restrict__ xp) {
+                                  XT* __restrict__ xp, float* __restrict__ yp) {
   const int stride = gridDim.x * blockDim.x;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) xp[i] = x[perm[i]];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    xp[i] = x[perm[i]];
+    yp[i] = 0.0f;  // the panels accumulate into yp
+  }
 }
 
 // y[j] = yp[inv[j]] (the output back in the caller's vertex order)
@@ -334,39 +341,49 @@ int launch_syprd(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* c
 namespace {
 
 // The panel kernel over a prepared matrix in its own vertex order.
-int panel_call(const Tensor* t, const void* x, systec_dtype xdt, float* y, hipStream_t s) {
-  int rc = launch_fill_f32(y, t->dim, s);
-  if (rc != SYSTEC_OK || t->nchunks == 0) return rc;
-  const size_t lds = static_cast<size_t>(t->panel_rows) * sizeof(double);
-  const int n = static_cast<int>(t->dim);
+template <typename XT, bool kStageX>
+int panel_launch(const Tensor* t, const XT* x, float* y, hipStream_t s) {
+  const size_t H = static_cast<size_t>(t->panel_rows);
+  const size_t lds = H * sizeof(double) + (kStageX ? H * sizeof(XT) : 0);
+  const void* kern = reinterpret_cast<const void*>(ssymv_panel_kernel<XT, kStageX>);
   // more than the default 64 KiB of dynamic LDS
-  rc = check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(ssymv_panel_kernel<float>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     static_cast<int>(lds)),
-                 "hipFuncSetAttribute(dynamic LDS)");
-  if (!rc)
-    rc = check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(ssymv_panel_kernel<uint16_t>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       static_cast<int>(lds)),
-                   "hipFuncSetAttribute(dynamic LDS)");
+  const int rc = check_hip(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               static_cast<int>(lds)),
+                           "hipFuncSetAttribute(dynamic LDS)");
   if (rc) return rc;
   LaunchTimer timer(s);
-  if (xdt == SYSTEC_F32)
-    ssymv_panel_kernel<float><<<dim3(t->nchunks), dim3(kPanelThreads), lds, s>>>(
-        n, t->panel_rows, t->chunk_panel, t->chunk_tile_begin, t->chunk_tile_end, t->pcol,
-        t->prow, t->pval, static_cast<const float*>(x), y);
-  else
-    ssymv_panel_kernel<uint16_t><<<dim3(t->nchunks), dim3(kPanelThreads), lds, s>>>(
-        n, t->panel_rows, t->chunk_panel, t->chunk_tile_begin, t->chunk_tile_end, t->pcol,
-        t->prow, t->pval, static_cast<const uint16_t*>(x), y);
+  ssymv_panel_kernel<XT, kStageX><<<dim3(t->nchunks), dim3(kPanelThreads), lds, s>>>(
+      static_cast<int>(t->dim), t->panel_rows, t->chunk_panel, t->chunk_tile_begin,
+      t->chunk_tile_end, t->pcol, t->prow, t->pval, x, y);
   return check_launch("ssymv panel kernel");
+}
+
+// y is cleared first unless the caller has done so (y_clear).
+int panel_call(const Tensor* t, const void* x, systec_dtype xdt, float* y, bool y_clear,
+               hipStream_t s) {
+  int rc = y_clear ? SYSTEC_OK : launch_fill_f32(y, t->dim, s);
+  if (rc != SYSTEC_OK || t->nchunks == 0) return rc;
+  if (xdt == SYSTEC_F32) return panel_launch<float, false>(t, static_cast<const float*>(x), y, s);
+  // BF16 x: the panel's slice of x goes to LDS beside the row sums when the
+  // device allows that much per workgroup (16384 rows: 160 KiB)
+  int dev = 0;
+  int limit = 0;
+  rc = check_hip(hipGetDevice(&dev), "hipGetDevice");
+  if (!rc)
+    rc = check_hip(hipDeviceGetAttribute(&limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev),
+                   "hipDeviceGetAttribute(max shared memory)");
+  if (rc) return rc;
+  const size_t staged = static_cast<size_t>(t->panel_rows) * (sizeof(double) + sizeof(uint16_t));
+  const uint16_t* xb = static_cast<const uint16_t*>(x);
+  return staged <= static_cast<size_t>(limit) ? panel_launch<uint16_t, true>(t, xb, y, s)
+                                              : panel_launch<uint16_t, false>(t, xb, y, s);
 }
 
 }  // namespace
 
 int launch_ssymv_panel(const Tensor* t, const void* x, systec_dtype xdt, float* y,
                        hipStream_t s) {
-  if (!t->relabeled) return panel_call(t, x, xdt, y, s);
+  if (!t->relabeled) return panel_call(t, x, xdt, y, false, s);
   // relabeled matrix: x in the prepared order, the panels, y back in the
   // caller's order (stream-ordered scratch)
   const int n = static_cast<int>(t->dim);
@@ -385,12 +402,12 @@ int launch_ssymv_panel(const Tensor* t, const void* x, systec_dtype xdt, float* 
   const int grid = static_cast<int>(std::min<int64_t>((n + 255) / 256, 8192));
   if (xdt == SYSTEC_F32)
     permute_in_kernel<float><<<grid, 256, 0, s>>>(n, t->perm, static_cast<const float*>(x),
-                                                 static_cast<float*>(xp));
+                                                 static_cast<float*>(xp), yp);
   else
     permute_in_kernel<uint16_t><<<grid, 256, 0, s>>>(n, t->perm, static_cast<const uint16_t*>(x),
-                                                    static_cast<uint16_t*>(xp));
+                                                    static_cast<uint16_t*>(xp), yp);
   rc = check_launch("ssymv input permutation");
-  if (!rc) rc = panel_call(t, xp, xdt, yp, s);
+  if (!rc) rc = panel_call(t, xp, xdt, yp, true, s);
   if (!rc) {
     permute_out_kernel<<<grid, 256, 0, s>>>(n, t->inv, yp, y);
     rc = check_launch("ssymv output permutation");
