@@ -117,6 +117,72 @@ def timed(fn, steps, warmup):
     return (time.perf_counter() - t0) / steps
 
 
+def degree_ordered_csr(torch, rp, col, val, perm):
+    """Upper-triangle CSR of P A P^T for perm (position -> caller's vertex), on
+    the device: the comparison kernels then see the order the symmetric path
+    stores its matrix in (setup, not timed)."""
+    n = rp.numel() - 1
+    dev = rp.device
+    inv = torch.empty(n, dtype=torch.int64, device=dev)
+    inv[perm.long()] = torch.arange(n, dtype=torch.int64, device=dev)
+    rows = torch.repeat_interleave(torch.arange(n, dtype=torch.int64, device=dev),
+                                   (rp[1:] - rp[:-1]).long())
+    r2, c2 = inv[rows], inv[col.long()]
+    del rows
+    lo, hi = torch.minimum(r2, c2), torch.maximum(r2, c2)
+    key, order = torch.sort(lo * n + hi)
+    del lo, hi, r2, c2
+    lo, hi = key // n, key % n
+    rp2 = torch.zeros(n + 1, dtype=torch.int64, device=dev)
+    rp2[1:] = torch.cumsum(torch.bincount(lo, minlength=n), 0)
+    return rp2.int(), hi.int(), val[order].contiguous()
+
+
+def rocsparse_spmv(torch, rp, col, val, x, steps, warmup):
+    """rocSPARSE general CSR SpMV (adaptive algorithm, FP32) on a full matrix:
+    an outside reference point for the comparison, not part of the library.
+    Returns (seconds per call, y)."""
+    import ctypes
+    from ctypes import byref, c_float, c_int, c_int64, c_size_t, c_void_p
+    L = ctypes.CDLL(os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib", "librocsparse.so"))
+    n, nnz = rp.numel() - 1, col.numel()
+    I32, F32, OP_NONE, ADAPTIVE = 2, 151, 111, 2
+    P = lambda t: c_void_p(t.data_ptr())  # noqa: E731
+
+    def ok(st, what):
+        if st != 0:
+            raise RuntimeError(f"rocsparse {what}: status {st}")
+
+    h, mat, xv, yv = c_void_p(), c_void_p(), c_void_p(), c_void_p()
+    y = torch.empty(n, dtype=torch.float32, device=x.device)
+    ok(L.rocsparse_create_handle(byref(h)), "create_handle")
+    try:
+        ok(L.rocsparse_set_stream(h, c_void_p(torch.cuda.current_stream().cuda_stream)), "set_stream")
+        ok(L.rocsparse_create_csr_descr(byref(mat), c_int64(n), c_int64(n), c_int64(nnz), P(rp), P(col),
+                                        P(val), c_int(I32), c_int(I32), c_int(0), c_int(F32)), "csr descr")
+        ok(L.rocsparse_create_dnvec_descr(byref(xv), c_int64(n), P(x), c_int(F32)), "x descr")
+        ok(L.rocsparse_create_dnvec_descr(byref(yv), c_int64(n), P(y), c_int(F32)), "y descr")
+        alpha, beta, size = c_float(1.0), c_float(0.0), c_size_t(0)
+
+        def call(stage, buf):
+            return L.rocsparse_spmv(h, c_int(OP_NONE), byref(alpha), mat, xv, byref(beta), yv,
+                                    c_int(F32), c_int(ADAPTIVE), c_int(stage), byref(size), buf)
+        ok(call(1, None), "buffer size")
+        buf = torch.empty(max(1, size.value), dtype=torch.uint8, device=x.device)
+        ok(call(2, P(buf)), "preprocess")
+        ok(call(3, P(buf)), "compute")
+        sec = timed(lambda: call(3, P(buf)), steps, warmup)
+        torch.cuda.synchronize()
+        return sec, y
+    finally:
+        for v in (xv, yv):
+            if v.value:
+                L.rocsparse_destroy_dnvec_descr(v)
+        if mat.value:
+            L.rocsparse_destroy_spmat_descr(mat)
+        L.rocsparse_destroy_handle(h)
+
+
 def kernel_ms(fn, reps):
     """Average duration of the library's hot-kernel launches inside fn()."""
     import paper_2406_09266_amd as systec
@@ -267,17 +333,51 @@ def main():
     if not a.no_compare:
         try:
             if a.workload.startswith("ssymv"):
-                frp, fcol, fval = systec.expand_csr(rp, col, val)
+                # the full matrix in the order the symmetric path stores it,
+                # and in the caller's order
+                perm = A.vertex_order()
+                orders = {"vertex": (rp, col, val, x)}
+                if perm is not None:
+                    rp2, col2, val2 = degree_ordered_csr(torch, rp, col, val, perm)
+                    orders["degree"] = (rp2, col2, val2, x[perm.long()].contiguous())
+                same = "degree" if perm is not None else "vertex"
                 yf = torch.empty_like(y)
-                cstep = lambda: systec.spmv_csr(frp, fcol, fval, x, out=yf)  # noqa: E731
+                forms, full = {}, {}
+                for name, (r_, c_, v_, x_) in orders.items():
+                    full[name] = systec.expand_csr(r_, c_, v_) + (x_,)
+                    frp, fcol, fval, xo = full[name]
+                    forms[name] = timed(lambda: systec.spmv_csr(frp, fcol, fval, xo, out=yf),  # noqa: E731
+                                        a.steps, a.warmup)
+                csec = forms[same]
+                out["nonsymmetric"] = {"ms_per_step": csec * 1e3, "effective_nnz_per_s": eff / csec,
+                                       "speedup_symmetric": csec / sec, "vertex_order": same,
+                                       "ms_by_vertex_order": {k: v * 1e3 for k, v in forms.items()}}
+                # an outside reference: rocSPARSE's general SpMV (adaptive,
+                # FP32 x holding the same values) on the same full matrices
+                try:
+                    rs, diffs = {}, {}
+                    for name, (frp, fcol, fval, xo) in full.items():
+                        rsec, yr = rocsparse_spmv(torch, frp, fcol, fval, xo.float(), a.steps, a.warmup)
+                        rs[name] = rsec
+                        if name == "vertex":
+                            prepared()
+                            torch.cuda.synchronize()
+                            diffs[name] = (torch.linalg.norm(yr - y) / torch.linalg.norm(y)).item()
+                    best = min(rs.values())
+                    out["rocsparse_general_spmv"] = {
+                        "alg": "adaptive", "x_dtype": "f32", "ms_by_vertex_order": {k: v * 1e3 for k, v in rs.items()},
+                        "rel_diff_vs_symmetric": diffs, "speedup_symmetric_vs_best": best / sec}
+                except Exception as e:  # report, do not hide
+                    out["rocsparse_general_spmv"] = {"error": str(e)}
+                del full, orders
             else:
                 fidx, fval = systec.expand_coo(idx, val, I)
                 Cf = torch.empty_like(C)
                 cstep = lambda: systec.mttkrp_full(fidx, fval, B, out=Cf)  # noqa: E731
-            csec = timed(cstep, a.steps, a.warmup)
-            out["nonsymmetric"] = {"ms_per_step": csec * 1e3, "effective_nnz_per_s": eff / csec,
-                                   "speedup_symmetric": csec / sec}
-            del cstep
+                csec = timed(cstep, a.steps, a.warmup)
+                out["nonsymmetric"] = {"ms_per_step": csec * 1e3, "effective_nnz_per_s": eff / csec,
+                                       "speedup_symmetric": csec / sec}
+                del cstep
         except Exception as e:  # report, do not hide
             out["nonsymmetric"] = {"error": str(e)}
 

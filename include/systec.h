@@ -292,6 +292,13 @@ SYSTEC_API int systec_tensor_create_coo(int order, int64_t I, int64_t nnz,
  * the expanded tensor), device bytes held. Any output pointer may be NULL. */
 SYSTEC_API int systec_tensor_info(const systec_tensor* t, int* order, int64_t* dim,
                                   int64_t* nnz, int64_t* effective_nnz, uint64_t* bytes);
+/* The vertex order a prepared matrix is stored in. *relabeled (may be NULL)
+ * is 1 if systec_tensor_create_csr_ex relabeled it, else 0. If perm is not
+ * NULL and the matrix was relabeled, perm (device int32[n], caller-owned)
+ * receives the order: perm[i] is the caller's vertex stored at position i,
+ * written on `stream` (asynchronous). Not a matrix: SYSTEC_EINVAL. */
+SYSTEC_API int systec_tensor_vertex_order(const systec_tensor* t, int* relabeled, int32_t* perm,
+                                          systec_stream stream);
 SYSTEC_API int systec_tensor_destroy(systec_tensor* t);
 /* y = A x for a prepared matrix; x, y as for systec_ssymv. */
 SYSTEC_API int systec_ssymv_t(const systec_tensor* t, const void* x, systec_dtype xdt, float* y,

@@ -291,6 +291,19 @@ class Tensor:
              _p(val), code, _stream(stream), ctypes.byref(h))
         return cls(h)
 
+    def vertex_order(self, stream=None):
+        """None if the matrix is stored in the caller's vertex order, else
+        perm (int32 on the device): perm[i] is the caller's vertex stored at
+        position i."""
+        torch = _torch()
+        rel = ctypes.c_int()
+        call("systec_tensor_vertex_order", self._h, ctypes.byref(rel), None, _stream(stream))
+        if not rel.value:
+            return None
+        perm = torch.empty(self.dim, dtype=torch.int32, device="cuda")
+        call("systec_tensor_vertex_order", self._h, None, _p(perm), _stream(stream))
+        return perm
+
     @classmethod
     def from_coo(cls, idx, val, I, stream=None):
         torch = _torch()

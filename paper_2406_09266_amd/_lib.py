@@ -50,6 +50,7 @@ SIGNATURES = {
     "systec_tensor_create_coo": [I32, I64, I64, PP, P, P, PP],
     "systec_tensor_info": [P, ctypes.POINTER(ctypes.c_int), PI64, PI64, PI64,
                            ctypes.POINTER(ctypes.c_uint64)],
+    "systec_tensor_vertex_order": [P, ctypes.POINTER(ctypes.c_int), P, P],
     "systec_tensor_destroy": [P],
     "systec_ssymv_t": [P, P, I32, P, P],
     "systec_mttkrp_t": [P, P, I32, I64, P, P],

@@ -412,6 +412,18 @@ int systec_tensor_info(const systec_tensor* t, int* order, int64_t* dim, int64_t
   return SYSTEC_OK;
 }
 
+int systec_tensor_vertex_order(const systec_tensor* t, int* relabeled, int32_t* perm,
+                               systec_stream stream) {
+  if (!t || !t->impl) return fail(SYSTEC_EINVAL, "systec_tensor_vertex_order: NULL handle");
+  if (t->impl->kind != 0) return fail(SYSTEC_EINVAL, "systec_tensor_vertex_order: not a matrix");
+  const bool r = t->impl->relabeled;
+  if (relabeled) *relabeled = r ? 1 : 0;
+  if (!perm || !r || t->impl->dim == 0) return SYSTEC_OK;
+  return check_hip(hipMemcpyAsync(perm, t->impl->perm, static_cast<size_t>(t->impl->dim) * sizeof(int32_t),
+                                  hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)),
+                   "hipMemcpyAsync(vertex order)");
+}
+
 int systec_tensor_destroy(systec_tensor* t) {
   if (!t) return SYSTEC_OK;
   tensor_free(t->impl);

@@ -75,6 +75,27 @@ def test_prepared_ssymv_vertex_order(case, relabel, xdtype):
     A.close()
 
 
+@pytest.mark.parametrize("relabel", [True, False])
+def test_prepared_ssymv_reports_vertex_order(relabel):
+    """The stored order is a permutation by descending degree, ties in vertex
+    order (degree counted on the CPU from the stored triangle)."""
+    m = synth.ssymv_rmat(scale=12, batch=1 << 15, seed=56)
+    n = m["n"]
+    A = systec.Tensor.from_csr(dev(m["rowptr"]), dev(m["col"]), dev(m["val"].astype(np.float32)),
+                               relabel=relabel)
+    perm = A.vertex_order()
+    A.close()
+    if not relabel:
+        assert perm is None
+        return
+    perm = perm.cpu().numpy().astype(np.int64)
+    assert np.array_equal(np.sort(perm), np.arange(n))
+    rows = np.repeat(np.arange(n), np.diff(m["rowptr"]))
+    col = m["col"].astype(np.int64)
+    deg = np.bincount(rows, minlength=n) + np.bincount(col[col != rows], minlength=n)
+    assert np.array_equal(perm, np.argsort(-deg, kind="stable"))
+
+
 def test_relabeled_matrix_is_not_served():
     m = synth.ssymv_rmat(scale=12, batch=1 << 15, seed=55)
     A = systec.Tensor.from_csr(dev(m["rowptr"]), dev(m["col"]), dev(m["val"].astype(np.float32)),
