@@ -280,8 +280,9 @@ SYSTEC_API int systec_tensor_create_csr(int64_t n, int64_t nnz, const int32_t* r
  * its stream, with stream-ordered scratch). relabel = 0 keeps the order
  * (what systec_tensor_create_csr does); relabel = -1 relabels when the
  * largest degree exceeds 8 times the mean (power-law graphs). Anything else
- * is SYSTEC_EINVAL. A relabeled matrix cannot be registered with a server
- * (SYSTEC_EINVAL). */
+ * is SYSTEC_EINVAL. A server serves a relabeled matrix too: each of its
+ * requests then holds two more n-element vectors, the input and the output
+ * in the stored order (stream-ordered, counted against the budget). */
 SYSTEC_API int systec_tensor_create_csr_ex(int64_t n, int64_t nnz, const int32_t* rowptr,
                                            const int32_t* col, const float* val, int relabel,
                                            systec_stream stream, systec_tensor** out);

@@ -281,7 +281,8 @@ class Tensor:
         """relabel: True stores the matrix with its vertices ordered by degree
         (each ssymv then permutes x in and y out; faster on power-law
         graphs), False keeps the order, None lets the library decide from the
-        degree skew. A relabeled matrix cannot be registered with a Server."""
+        degree skew. A Server serves a relabeled matrix with two more
+        n-element vectors per request (counted against its budget)."""
         torch = _torch()
         _dev(rowptr, torch.int32, "rowptr"), _dev(col, torch.int32, "col")
         _dev(val, torch.float32, "val")

@@ -141,6 +141,11 @@ int tensor_create_csr(int64_t n, int64_t nnz, const int32_t* rowptr, const int32
 int tensor_create_coo(int order, int64_t I, int64_t nnz, const int32_t* const* idx,
                       const float* val, hipStream_t s, Tensor** out);
 void tensor_free(Tensor* t);
+// Vertex permutations of a relabeled matrix (n elements): xp[i] = x[perm[i]]
+// with yp cleared, and y[j] = yp[inv[j]].
+int launch_permute_in(int n, const int32_t* perm, const void* x, systec_dtype xdt, void* xp,
+                      float* yp, hipStream_t s);
+int launch_permute_out(int n, const int32_t* inv, const float* yp, float* y, hipStream_t s);
 int launch_ssymv_panel(const Tensor* t, const void* x, systec_dtype xdt, float* y,
                        hipStream_t s);
 int launch_mttkrp_views(const Tensor* t, const void* B, systec_dtype bdt, int64_t R, float* C,

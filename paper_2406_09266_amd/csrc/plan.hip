@@ -51,13 +51,21 @@ __global__ void entry_rows_kernel(int n, int nnz, const int32_t* __restrict__ ro
 // ---- vertex relabeling by degree ----
 // deg[v]: stored entries in row v plus off-diagonal stored entries in column
 // v (the vertex's degree in the symmetric matrix).
-__global__ void degree_kernel(int nnz, const int32_t* __restrict__ rows,
-                              const int32_t* __restrict__ col, int32_t* __restrict__ deg) {
+// The stored entries of row v, then (col_degree_kernel) one more for each
+// off-diagonal entry in column v: the rows are sorted, so counting them by
+// atomics would put a whole wave on one address.
+__global__ void row_degree_kernel(int n, const int32_t* __restrict__ rowptr,
+                                  int32_t* __restrict__ deg) {
   const int stride = gridDim.x * blockDim.x;
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += stride) {
-    atomicAdd(deg + rows[e], 1);
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
+    deg[v] = rowptr[v + 1] - rowptr[v];
+}
+
+__global__ void col_degree_kernel(int nnz, const int32_t* __restrict__ rows,
+                                  const int32_t* __restrict__ col, int32_t* __restrict__ deg) {
+  const int stride = gridDim.x * blockDim.x;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += stride)
     if (col[e] != rows[e]) atomicAdd(deg + col[e], 1);
-  }
 }
 
 // Largest degree (one atomic per workgroup) and the sort keys: descending
@@ -272,8 +280,9 @@ void tensor_free(Tensor* t) {
 // (old -> new) on the tensor.
 constexpr int kRelabelSkew = 8;
 
-static int relabel_by_degree(Tensor* t, int n, int nnz, int32_t* rows, const int32_t* col,
-                             int relabel, Scratch& sc, hipStream_t s, const int32_t** keycol) {
+static int relabel_by_degree(Tensor* t, int n, int nnz, const int32_t* rowptr, int32_t* rows,
+                             const int32_t* col, int relabel, Scratch& sc, hipStream_t s,
+                             const int32_t** keycol) {
   int32_t *deg = nullptr, *col2 = nullptr;
   uint32_t *kin = nullptr, *kout = nullptr, *vin = nullptr;
   int* d_max = nullptr;
@@ -282,10 +291,10 @@ static int relabel_by_degree(Tensor* t, int n, int nnz, int32_t* rows, const int
   if (!rc) rc = sc.alloc(&kout, n);
   if (!rc) rc = sc.alloc(&vin, n);
   if (!rc) rc = sc.alloc(&d_max, 1);
-  if (!rc) rc = check_hip(hipMemsetAsync(deg, 0, n * sizeof(int32_t), s), "hipMemsetAsync");
   if (!rc) rc = check_hip(hipMemsetAsync(d_max, 0, sizeof(int), s), "hipMemsetAsync");
   if (rc) return rc;
-  degree_kernel<<<grid_for(nnz, 256), 256, 0, s>>>(nnz, rows, col, deg);
+  row_degree_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, rowptr, deg);
+  col_degree_kernel<<<grid_for(nnz, 256), 256, 0, s>>>(nnz, rows, col, deg);
   degree_keys_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, deg, kin, vin, d_max);
   if ((rc = check_launch("degree kernels"))) return rc;
   if (relabel < 0) {
@@ -354,7 +363,8 @@ int tensor_create_csr(int64_t n, int64_t nnz, const int32_t* rowptr, const int32
     entry_rows_kernel<<<grid_for(nnz, 256), 256, 0, s>>>(ni, nz, rowptr, rows);
     rc = check_launch("entry row kernel");
     const int32_t* keycol = col;
-    if (!rc && relabel != 0) rc = relabel_by_degree(t, ni, nz, rows, col, relabel, sc, s, &keycol);
+    if (!rc && relabel != 0)
+      rc = relabel_by_degree(t, ni, nz, rowptr, rows, col, relabel, sc, s, &keycol);
     if (!rc) {
       panel_keys_kernel<<<grid_for(nnz, 256), 256, 0, s>>>(nz, hbits, rows, keycol, kin, vin);
       rc = check_launch("panel key kernels");

@@ -6,13 +6,19 @@
 // and then its step kernels (one per variant, one workgroup per work item;
 // the requests and their unit ranges travel as kernel arguments), each
 // stream closed by an event. A few steps are in flight (max_inflight), so
-// the host builds the next step while others run.
+// the host builds the next step while others run. A request on a matrix
+// stored with its vertices relabeled gets two stream-ordered scratch vectors
+// at admission (its input in the stored order, and the output there, both
+// filled by one permutation kernel in place of the zero kernel); the step
+// that runs its last unit permutes the output back and frees them, before
+// the step's event.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstring>
 #include <memory>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "common.h"
@@ -76,6 +82,10 @@ class GpuExecutor {
   ~GpuExecutor() {
     for (hipStream_t st : streams_)
       if (st) (void)hipStreamSynchronize(st);
+    for (auto& kv : scratch_) {  // requests that failed before their last unit
+      (void)hipFree(kv.second.xp);
+      (void)hipFree(kv.second.yp);
+    }
     for (auto& evs : ev_)
       for (hipEvent_t ev : evs)
         if (ev) (void)hipEventDestroy(ev);
@@ -132,7 +142,8 @@ class GpuExecutor {
   uint64_t request_bytes(const serve::TensorEntry& t, int dtype, int64_t R) const {
     const uint64_t es = dtype == SYSTEC_BF16 ? 2 : 4;
     const uint64_t cols = t.kind == 0 ? 1 : static_cast<uint64_t>(R);
-    return static_cast<uint64_t>(t.dim) * cols * (es + 4);  // input + FP32 output
+    const uint64_t b = static_cast<uint64_t>(t.dim) * cols * (es + 4);  // input + FP32 output
+    return permuted(t) ? 2 * b : b;  // and their copies in the stored vertex order
   }
 
   int launch(const serve::Plan& plan, std::string* err) {
@@ -177,6 +188,11 @@ class GpuExecutor {
         for (size_t k = 0; k < plan.zero.size() && !rc; ++k) {
           const serve::Request* r = plan.zero[k];
           if (kind_of(static_cast<const Tensor*>(r->tensor->payload)) != g) continue;
+          if (permuted(*r->tensor)) {
+            rc = begin_permuted(*r, st);
+            ++launched;
+            continue;
+          }
           z.ptr[z.n] = r->out;
           z.count[z.n] = r->tensor->dim * (r->tensor->kind == 0 ? 1 : r->R);
           if (++z.n == kStepReqs) {
@@ -201,6 +217,11 @@ class GpuExecutor {
             q.t = sh.t->d_serve;
             q.in = sh.req->in;
             q.out = sh.req->out;
+            const auto sc = scratch_.find(sh.req->id);
+            if (sc != scratch_.end()) {  // relabeled matrix: the stored vertex order
+              q.in = sc->second.xp;
+              q.out = sc->second.yp;
+            }
             q.unit0 = sh.unit0;
             q.item0 = a.nitems;
             q.R = static_cast<int32_t>(sh.req->R);
@@ -216,6 +237,22 @@ class GpuExecutor {
             rc = launch_serve_step(g == 0 ? 0 : g + 2, v, a, st);
             ++launched;
           }
+        }
+        // relabeled matrices whose last unit ran in this step: output back
+        // in the caller's vertex order, scratch released (stream-ordered)
+        for (size_t k = 0; g == 0 && k < shares.size() && !rc; ++k) {
+          const Share& sh = shares[k];
+          if (kind_of(sh.t) != 0) continue;
+          const auto sc = scratch_.find(sh.req->id);
+          if (sc == scratch_.end()) continue;
+          if (static_cast<size_t>(sh.unit0) + sh.count != sh.req->tensor->units.size()) continue;
+          rc = launch_permute_out(static_cast<int>(sh.t->dim), sh.t->inv, sc->second.yp,
+                                  sh.req->out, st);
+          const int rc2 = check_hip(hipFreeAsync(sc->second.xp, st), "hipFreeAsync");
+          const int rc3 = check_hip(hipFreeAsync(sc->second.yp, st), "hipFreeAsync");
+          scratch_.erase(sc);
+          if (!rc) rc = rc2 ? rc2 : rc3;
+          ++launched;
         }
         // a stream with no work this step records no event (queries of it
         // report done)
@@ -266,6 +303,38 @@ class GpuExecutor {
   hipStream_t stream() const { return stream_; }
 
  private:
+  // A matrix stored with its vertices relabeled and with work to run: its
+  // requests compute in the stored order.
+  static bool permuted(const serve::TensorEntry& t) {
+    const Tensor* tt = static_cast<const Tensor*>(t.payload);
+    return t.kind == 0 && tt && tt->relabeled && !t.units.empty();
+  }
+
+  // Scratch of a newly admitted request on a relabeled matrix, filled on st.
+  int begin_permuted(const serve::Request& r, hipStream_t st) {
+    const Tensor* t = static_cast<const Tensor*>(r.tensor->payload);
+    const auto n = static_cast<size_t>(t->dim);
+    const systec_dtype dt = r.dtype == SYSTEC_BF16 ? SYSTEC_BF16 : SYSTEC_F32;
+    Scratch sc;
+    int rc = check_hip(hipMallocAsync(&sc.xp, n * (dt == SYSTEC_BF16 ? 2 : 4), st),
+                       "hipMallocAsync(serving scratch)");
+    if (rc) return rc;
+    rc = check_hip(hipMallocAsync(reinterpret_cast<void**>(&sc.yp), n * sizeof(float), st),
+                   "hipMallocAsync(serving scratch)");
+    if (rc) {
+      (void)hipFreeAsync(sc.xp, st);
+      return rc;
+    }
+    scratch_[r.id] = sc;
+    return launch_permute_in(static_cast<int>(n), t->perm, r.in, dt, sc.xp, sc.yp, st);
+  }
+
+  struct Scratch {
+    void* xp = nullptr;   // the input in the stored vertex order
+    float* yp = nullptr;  // the output in the stored vertex order
+  };
+  std::unordered_map<int64_t, Scratch> scratch_;  // by request id
+
   int device_ = 0;
   hipStream_t streams_[4] = {nullptr, nullptr, nullptr, nullptr};  // per kernel kind
   hipStream_t stream_ = nullptr;                                   // streams_[0]
@@ -317,10 +386,6 @@ int systec_serve_create(const systec_serve_config* cfg, systec_server** out) {
 int systec_serve_register(systec_server* s, systec_tensor* t, int64_t* tensor_id) {
   if (!s || !t || !t->impl || !tensor_id)
     return serve_fail(SYSTEC_EINVAL, "systec_serve_register: NULL argument");
-  if (t->impl->relabeled)
-    return serve_fail(SYSTEC_EINVAL,
-                      "systec_serve_register: the matrix was prepared with its vertices relabeled; "
-                      "create it with systec_tensor_create_csr_ex(..., relabel = 0, ...) to serve it");
   auto e = std::make_shared<serve::TensorEntry>();
   std::string err;
   if (!t->impl->d_serve) {

@@ -381,6 +381,26 @@ int panel_call(const Tensor* t, const void* x, systec_dtype xdt, float* y, bool 
 
 }  // namespace
 
+int launch_permute_in(int n, const int32_t* perm, const void* x, systec_dtype xdt, void* xp,
+                      float* yp, hipStream_t s) {
+  if (n == 0) return SYSTEC_OK;
+  const int grid = static_cast<int>(std::min<int64_t>((n + 255) / 256, 8192));
+  if (xdt == SYSTEC_F32)
+    permute_in_kernel<float><<<grid, 256, 0, s>>>(n, perm, static_cast<const float*>(x),
+                                                 static_cast<float*>(xp), yp);
+  else
+    permute_in_kernel<uint16_t><<<grid, 256, 0, s>>>(n, perm, static_cast<const uint16_t*>(x),
+                                                    static_cast<uint16_t*>(xp), yp);
+  return check_launch("ssymv input permutation");
+}
+
+int launch_permute_out(int n, const int32_t* inv, const float* yp, float* y, hipStream_t s) {
+  if (n == 0) return SYSTEC_OK;
+  const int grid = static_cast<int>(std::min<int64_t>((n + 255) / 256, 8192));
+  permute_out_kernel<<<grid, 256, 0, s>>>(n, inv, yp, y);
+  return check_launch("ssymv output permutation");
+}
+
 int launch_ssymv_panel(const Tensor* t, const void* x, systec_dtype xdt, float* y,
                        hipStream_t s) {
   if (!t->relabeled) return panel_call(t, x, xdt, y, false, s);
@@ -399,19 +419,9 @@ int launch_ssymv_panel(const Tensor* t, const void* x, systec_dtype xdt, float* 
     (void)hipFreeAsync(xp, s);
     return rc;
   }
-  const int grid = static_cast<int>(std::min<int64_t>((n + 255) / 256, 8192));
-  if (xdt == SYSTEC_F32)
-    permute_in_kernel<float><<<grid, 256, 0, s>>>(n, t->perm, static_cast<const float*>(x),
-                                                 static_cast<float*>(xp), yp);
-  else
-    permute_in_kernel<uint16_t><<<grid, 256, 0, s>>>(n, t->perm, static_cast<const uint16_t*>(x),
-                                                    static_cast<uint16_t*>(xp), yp);
-  rc = check_launch("ssymv input permutation");
+  rc = launch_permute_in(n, t->perm, x, xdt, xp, yp, s);
   if (!rc) rc = panel_call(t, xp, xdt, yp, true, s);
-  if (!rc) {
-    permute_out_kernel<<<grid, 256, 0, s>>>(n, t->inv, yp, y);
-    rc = check_launch("ssymv output permutation");
-  }
+  if (!rc) rc = launch_permute_out(n, t->inv, yp, y, s);
   const int rc2 = check_hip(hipFreeAsync(xp, s), "hipFreeAsync");
   const int rc3 = check_hip(hipFreeAsync(yp, s), "hipFreeAsync");
   return rc ? rc : (rc2 ? rc2 : rc3);

@@ -96,14 +96,6 @@ def test_prepared_ssymv_reports_vertex_order(relabel):
     assert np.array_equal(perm, np.argsort(-deg, kind="stable"))
 
 
-def test_relabeled_matrix_is_not_served():
-    m = synth.ssymv_rmat(scale=12, batch=1 << 15, seed=55)
-    A = systec.Tensor.from_csr(dev(m["rowptr"]), dev(m["col"]), dev(m["val"].astype(np.float32)),
-                               relabel=True)
-    with systec.Server(budget_bytes=1 << 30) as srv:
-        with pytest.raises(systec.SystecError) as e:
-            srv.register(A)
-        assert "relabel" in str(e.value)
 
 
 def test_prepared_ssymv_empty_rows_and_panels():

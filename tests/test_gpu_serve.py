@@ -111,6 +111,59 @@ def test_mix_equals_alone_and_oracle(bf16, streams, inflight):
     assert st["p99_us"] >= st["p50_us"] > 0
 
 
+@pytest.mark.parametrize("bf16,step_work", [(False, 1 << 14), (True, 1 << 14), (True, 1 << 26)])
+def test_relabeled_matrices_are_served(bf16, step_work):
+    """Matrices stored with their vertices ordered by degree, served next to a
+    tensor: requests that span several steps (small step budget) and requests
+    that finish in one step both give the oracle's result."""
+    mats = [synth.ssymv_rmat(scale=14, batch=1 << 16, seed=91),
+            synth.ssymv_random_degree(20000, 10, seed=92)]
+    tens = [synth.sym_coo(3, 1500, 40000, 0.05, seed=93)]
+    reqs = _requests(mats, tens, 16, seed=17)
+    with systec.Server(budget_bytes=8 << 30, max_slots=6, step_work_nnz=step_work) as srv:
+        ids = [srv.register(systec.Tensor.from_csr(dev(m["rowptr"]), dev(m["col"]),
+                                                   dev(m["val"].astype(np.float32)), relabel=True))
+               for m in mats]
+        ids += _register(srv, [], tens)
+        outs = [_submit(srv, ids, mats, tens, r, bf16) for r in reqs]
+        for rid, _ in outs:
+            srv.wait(rid, 60_000_000)
+        st = srv.stats()
+    for r, (_, o) in zip(reqs, outs):
+        assert rel_err(o.cpu().numpy(), _oracle(mats, tens, r, bf16)) <= TOL32
+    assert st["completed"] == 16 and st["failed"] == 0
+
+
+def test_relabeled_request_counts_its_scratch():
+    """A request on a relabeled matrix holds its input and output twice (the
+    copies in the stored order): a budget with room for one plain request
+    next to the matrix rejects it."""
+    import torch
+    m = synth.ssymv_rmat(scale=13, batch=1 << 15, seed=95)
+
+    def tensor():
+        return systec.Tensor.from_csr(dev(m["rowptr"]), dev(m["col"]),
+                                      dev(m["val"].astype(np.float32)), relabel=True)
+    with systec.Server(budget_bytes=1 << 40) as probe:
+        probe.register(tensor())
+        resident = probe.stats()["bytes_in_use"]
+    one = m["n"] * (4 + 4)
+    x = dev(synth.dense_uniform(m["n"], seed=96).astype(np.float32))
+    y = torch.empty(m["n"], device="cuda")
+    torch.cuda.synchronize()
+    with systec.Server(budget_bytes=resident + one + one // 2) as srv:
+        tid = srv.register(tensor())
+        with pytest.raises(systec.SystecError) as e:
+            srv.submit(tid, x, y)
+        assert e.value.status_name == "SYSTEC_EBUDGET"
+    with systec.Server(budget_bytes=resident + 2 * one + one // 4) as srv:
+        tid = srv.register(tensor())
+        srv.wait(srv.submit(tid, x, y), 60_000_000)
+    want = oracle.ssymv(m["n"], m["rowptr"], m["col"], f32(m["val"]),
+                        synth.dense_uniform(m["n"], seed=96).astype(np.float32).astype(np.float64))[0]
+    assert rel_err(y.cpu().numpy(), want) <= TOL32
+
+
 def test_small_budget_blocks_and_resumes():
     import torch
     m = synth.ssymv_random_degree(200000, 16, seed=81)
