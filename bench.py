@@ -329,6 +329,17 @@ def main():
                 out["algos"][name] = {"error": str(e)}
         cfg["algo"] = algo
 
+    # ---- the scalar form s = x^T A x on the same matrix (no scattered writes) ----
+    if a.workload.startswith("ssymv"):
+        sp = torch.empty(1, dtype=torch.float64, device=dev)
+        s_alg = 4 * (n + 1) + 8 * U + n * sx
+        out["syprd"] = {"B_alg_bytes": s_alg}
+        for name, fn in (("prepared", lambda: A.syprd(x, out=sp)),
+                         ("oneshot", lambda: systec.syprd(rp, col, val, x, out=sp))):
+            ssec = timed(fn, a.steps, a.warmup)
+            out["syprd"][name] = {"ms_per_step": ssec * 1e3, "effective_nnz_per_s": eff / ssec,
+                                  "hbm_frac_alg": round(s_alg / ssec / 1e9 / HBM_PEAK_GBS, 4)}
+
     # ---- the non-symmetric comparison kernel on the expanded operand ----
     if not a.no_compare:
         try:

@@ -304,6 +304,12 @@ SYSTEC_API int systec_tensor_destroy(systec_tensor* t);
 /* y = A x for a prepared matrix; x, y as for systec_ssymv. */
 SYSTEC_API int systec_ssymv_t(const systec_tensor* t, const void* x, systec_dtype xdt, float* y,
                               systec_stream stream);
+/* s = x^T A x for a prepared matrix; x and out as for systec_syprd (one
+ * FP32 partial per chunk of the prepared format, FP64 final sum). A matrix
+ * stored with its vertices relabeled permutes x in first (stream-ordered
+ * scratch of n elements). */
+SYSTEC_API int systec_syprd_t(const systec_tensor* t, const void* x, systec_dtype xdt, double* out,
+                              systec_stream stream);
 /* C = MTTKRP for a prepared tensor; B, C as for systec_mttkrp. */
 SYSTEC_API int systec_mttkrp_t(const systec_tensor* t, const void* B, systec_dtype bdt,
                                int64_t R, float* C, systec_stream stream);

@@ -325,6 +325,16 @@ class Tensor:
         call("systec_ssymv_t", self._h, _p(x), _dtype_code(x), _p(y), _stream(stream))
         return y
 
+    def syprd(self, x, out=None, stream=None):
+        """x^T A x of the prepared matrix as a float64 device scalar."""
+        torch = _torch()
+        _dev(x, None, "x")
+        if self.order != 2 or x.numel() != self.dim:
+            raise ValueError("syprd needs a prepared matrix and x of n elements")
+        s = out if out is not None else torch.empty(1, dtype=torch.float64, device=x.device)
+        call("systec_syprd_t", self._h, _p(x), _dtype_code(x), _p(s), _stream(stream))
+        return s
+
     def mttkrp(self, B, out=None, stream=None, algo="auto"):
         """C = MTTKRP of the prepared tensor; algo: "auto", "views" (slot
         views), "lds" (slot views with B staged in LDS; small index spaces)

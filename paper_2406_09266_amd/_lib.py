@@ -51,6 +51,7 @@ SIGNATURES = {
     "systec_tensor_info": [P, ctypes.POINTER(ctypes.c_int), PI64, PI64, PI64,
                            ctypes.POINTER(ctypes.c_uint64)],
     "systec_tensor_vertex_order": [P, ctypes.POINTER(ctypes.c_int), P, P],
+    "systec_syprd_t": [P, P, I32, P, P],
     "systec_tensor_destroy": [P],
     "systec_ssymv_t": [P, P, I32, P, P],
     "systec_mttkrp_t": [P, P, I32, I64, P, P],

@@ -412,6 +412,15 @@ int systec_tensor_info(const systec_tensor* t, int* order, int64_t* dim, int64_t
   return SYSTEC_OK;
 }
 
+int systec_syprd_t(const systec_tensor* t, const void* x, systec_dtype xdt, double* out,
+                   systec_stream stream) {
+  if (!t || !t->impl) return fail(SYSTEC_EINVAL, "systec_syprd_t: NULL handle");
+  if (t->impl->kind != 0) return fail(SYSTEC_EINVAL, "systec_syprd_t: not a matrix");
+  if (!valid_dtype(xdt)) return fail(SYSTEC_EINVAL, "systec_syprd_t: unsupported dtype");
+  if (!x || !out) return fail(SYSTEC_EINVAL, "systec_syprd_t: NULL pointer");
+  return launch_syprd_panel(t->impl, x, xdt, out, static_cast<hipStream_t>(stream));
+}
+
 int systec_tensor_vertex_order(const systec_tensor* t, int* relabeled, int32_t* perm,
                                systec_stream stream) {
   if (!t || !t->impl) return fail(SYSTEC_EINVAL, "systec_tensor_vertex_order: NULL handle");

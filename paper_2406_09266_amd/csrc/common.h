@@ -141,8 +141,11 @@ int tensor_create_csr(int64_t n, int64_t nnz, const int32_t* rowptr, const int32
 int tensor_create_coo(int order, int64_t I, int64_t nnz, const int32_t* const* idx,
                       const float* val, hipStream_t s, Tensor** out);
 void tensor_free(Tensor* t);
+// s = x^T A x for a prepared matrix (out: device double[1]).
+int launch_syprd_panel(const Tensor* t, const void* x, systec_dtype xdt, double* out,
+                       hipStream_t s);
 // Vertex permutations of a relabeled matrix (n elements): xp[i] = x[perm[i]]
-// with yp cleared, and y[j] = yp[inv[j]].
+// with yp cleared (if not null), and y[j] = yp[inv[j]].
 int launch_permute_in(int n, const int32_t* perm, const void* x, systec_dtype xdt, void* xp,
                       float* yp, hipStream_t s);
 int launch_permute_out(int n, const int32_t* inv, const float* yp, float* y, hipStream_t s);

@@ -249,15 +249,68 @@ __global__ __launch_bounds__(kPanelThreads) void ssymv_panel_kernel(
                                  reinterpret_cast<XT*>(s_rows + H));
 }
 
+// SYPRD over the panel format: each stored entry gives a x[i] x[j], twice
+// off the diagonal (the scalar of the symmetric product, Sec. 3.2.2), summed
+// in FP32 per lane and wave, one FP32 partial per chunk (no scattered
+// writes at all); the panel's slice of x is staged in LDS (H elements) for
+// the row-side reads, as in the panel SSYMV.
+template <typename XT>
+__global__ __launch_bounds__(kPanelThreads) void syprd_panel_kernel(
+    int n, int H, const int32_t* __restrict__ chunk_panel,
+    const int32_t* __restrict__ chunk_tile_begin, const int32_t* __restrict__ chunk_tile_end,
+    const int32_t* __restrict__ pcol, const uint16_t* __restrict__ prow,
+    const float* __restrict__ pval, const XT* __restrict__ x, float* __restrict__ partial) {
+  extern __shared__ __align__(16) unsigned char s_dyn[];
+  XT* s_x = reinterpret_cast<XT*>(s_dyn);
+  __shared__ float s_part[kPanelThreads / kWave];
+  const int chunk = blockIdx.x;
+  const int r0 = chunk_panel[chunk] * H;
+  const int tb = chunk_tile_begin[chunk], te = chunk_tile_end[chunk];
+  for (int i = threadIdx.x; i < H; i += blockDim.x) s_x[i] = r0 + i < n ? x[r0 + i] : XT(0);
+  __syncthreads();
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
+  const int nw = blockDim.x / kWave;
+  float sum = 0.0f;
+  for (int tile = tb + w; tile < te; tile += nw) {
+    const int64_t base = static_cast<int64_t>(tile) * kTile + lane;
+    int c[kV];
+    int ro[kV];
+    float a[kV];
+#pragma unroll
+    for (int k = 0; k < kV; ++k) {  // coalesced: a step reads 64 consecutive entries
+      c[k] = pcol[base + k * kWave];
+      ro[k] = prow[base + k * kWave];
+      a[k] = pval[base + k * kWave];
+    }
+    float xc[kV];
+#pragma unroll
+    for (int k = 0; k < kV; ++k) xc[k] = load_f32(x, c[k]);  // padding: a valid position
+#pragma unroll
+    for (int k = 0; k < kV; ++k) {
+      const float f = c[k] != r0 + ro[k] ? 2.0f : 1.0f;
+      sum += f * a[k] * load_f32(s_x, ro[k]) * xc[k];
+    }
+  }
+  sum = wave_sum(sum);
+  if (lane == 0) s_part[w] = sum;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float t = 0.0f;
+    for (int i = 0; i < nw; ++i) t += s_part[i];
+    partial[chunk] = t;
+  }
+}
+
 // xp[i] = x[perm[i]] (the input in the prepared matrix's vertex order), and
-// yp cleared
+// yp cleared unless it is null
 template <typename XT>
 __global__ void permute_in_kernel(int n, const int32_t* __restrict__ perm, const XT* __restrict__ x,
                                   XT* __restrict__ xp, float* __restrict__ yp) {
   const int stride = gridDim.x * blockDim.x;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     xp[i] = x[perm[i]];
-    yp[i] = 0.0f;  // the panels accumulate into yp
+    if (yp) yp[i] = 0.0f;  // the panels accumulate into yp
   }
 }
 
@@ -399,6 +452,68 @@ int launch_permute_out(int n, const int32_t* inv, const float* yp, float* y, hip
   const int grid = static_cast<int>(std::min<int64_t>((n + 255) / 256, 8192));
   permute_out_kernel<<<grid, 256, 0, s>>>(n, inv, yp, y);
   return check_launch("ssymv output permutation");
+}
+
+namespace {
+
+// The prepared SYPRD over a matrix in its own vertex order (x already in
+// that order).
+int syprd_panel_call(const Tensor* t, const void* x, systec_dtype xdt, double* out,
+                     hipStream_t s) {
+  const int nch = std::max(1, t->nchunks);
+  float* partial = nullptr;
+  int rc = check_hip(hipMallocAsync(reinterpret_cast<void**>(&partial), nch * sizeof(float), s),
+                     "hipMallocAsync(syprd partials)");
+  if (rc) return rc;
+  if (t->nchunks == 0) {
+    fill_f32_kernel<<<1, 64, 0, s>>>(partial, 1);
+    rc = check_launch("syprd partial clear");
+  } else {
+    const size_t lds = static_cast<size_t>(t->panel_rows) * (xdt == SYSTEC_F32 ? 4 : 2);
+    const void* kern = xdt == SYSTEC_F32
+                           ? reinterpret_cast<const void*>(syprd_panel_kernel<float>)
+                           : reinterpret_cast<const void*>(syprd_panel_kernel<uint16_t>);
+    rc = check_hip(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       static_cast<int>(lds)),
+                   "hipFuncSetAttribute(dynamic LDS)");
+    if (!rc) {
+      LaunchTimer timer(s);
+      const int n = static_cast<int>(t->dim);
+      if (xdt == SYSTEC_F32)
+        syprd_panel_kernel<float><<<dim3(t->nchunks), dim3(kPanelThreads), lds, s>>>(
+            n, t->panel_rows, t->chunk_panel, t->chunk_tile_begin, t->chunk_tile_end, t->pcol,
+            t->prow, t->pval, static_cast<const float*>(x), partial);
+      else
+        syprd_panel_kernel<uint16_t><<<dim3(t->nchunks), dim3(kPanelThreads), lds, s>>>(
+            n, t->panel_rows, t->chunk_panel, t->chunk_tile_begin, t->chunk_tile_end, t->pcol,
+            t->prow, t->pval, static_cast<const uint16_t*>(x), partial);
+      rc = check_launch("syprd panel kernel");
+    }
+  }
+  if (!rc) {
+    reduce_partials_f64<<<dim3(1), dim3(1024), 0, s>>>(partial, nch, out);
+    rc = check_launch("syprd final reduction");
+  }
+  const int rc2 = check_hip(hipFreeAsync(partial, s), "hipFreeAsync(syprd partials)");
+  return rc ? rc : rc2;
+}
+
+}  // namespace
+
+int launch_syprd_panel(const Tensor* t, const void* x, systec_dtype xdt, double* out,
+                       hipStream_t s) {
+  if (!t->relabeled) return syprd_panel_call(t, x, xdt, out, s);
+  // relabeled matrix: s = x_p^T (P A P^T) x_p with x_p[i] = x[perm[i]]
+  const int n = static_cast<int>(t->dim);
+  if (n == 0) return syprd_panel_call(t, x, xdt, out, s);
+  void* xp = nullptr;
+  int rc = check_hip(hipMallocAsync(&xp, static_cast<size_t>(n) * (xdt == SYSTEC_F32 ? 4 : 2), s),
+                     "hipMallocAsync(permuted x)");
+  if (rc) return rc;
+  rc = launch_permute_in(n, t->perm, x, xdt, xp, nullptr, s);
+  if (!rc) rc = syprd_panel_call(t, xp, xdt, out, s);
+  const int rc2 = check_hip(hipFreeAsync(xp, s), "hipFreeAsync");
+  return rc ? rc : rc2;
 }
 
 int launch_ssymv_panel(const Tensor* t, const void* x, systec_dtype xdt, float* y,

@@ -76,6 +76,22 @@ def test_prepared_ssymv_vertex_order(case, relabel, xdtype):
 
 
 @pytest.mark.parametrize("relabel", [True, False])
+@pytest.mark.parametrize("xdtype", ["f32", "bf16"])
+def test_prepared_syprd(relabel, xdtype):
+    """x^T A x over the prepared format (vertex or degree order) against the
+    oracle, on a matrix of several panels and on one with a ragged tail."""
+    for m in (synth.ssymv_rmat(scale=15, batch=1 << 17, seed=57),
+              synth.ssymv_uniform(40001, 9, seed=58)):
+        A = systec.Tensor.from_csr(dev(m["rowptr"]), dev(m["col"]),
+                                   dev(m["val"].astype(np.float32)), relabel=relabel)
+        x, xref = _x(m, xdtype)
+        s = A.syprd(x).item()
+        want, scale, _ = oracle.syprd(m["n"], m["rowptr"], m["col"], f32(m["val"]), xref)
+        assert abs(s - want) <= TOL32 * scale
+        A.close()
+
+
+@pytest.mark.parametrize("relabel", [True, False])
 def test_prepared_ssymv_reports_vertex_order(relabel):
     """The stored order is a permutation by descending degree, ties in vertex
     order (degree counted on the CPU from the stored triangle)."""
