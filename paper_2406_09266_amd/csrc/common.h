@@ -200,6 +200,7 @@ constexpr int kPanelThreads = 1024;
 constexpr int kServeBlock = kPanelThreads;  // SSYMV step kernel
 constexpr int kServeMttkrpBlock = 256; // MTTKRP step kernel
 constexpr int kServeLds = kPanelRows * 8;  // bytes: the FP64 row sums of one panel
+constexpr int kServeLdsStaged = kPanelRows * (8 + 2);  // and the panel's BF16 x slice
 // Zeroes the outputs of newly admitted requests; runs on a stream before
 // its step launches.
 int launch_serve_prologue(const ZeroArgs& z, hipStream_t s);

@@ -7,6 +7,8 @@
 // hardware dispatcher balances the items and interleaves the workgroups of
 // the kinds that run at the same time; a prologue kernel on each stream
 // zeroes the outputs of newly admitted requests first.
+#include <atomic>
+
 #include "common.h"
 #include "mttkrp_device.h"
 #include "panel_device.h"
@@ -91,10 +93,13 @@ __device__ __forceinline__ void view_range(const ServeTensor* t, const ServeUnit
                                     0, q.R);
 }
 
-// SSYMV items need the panel's row sums in LDS (1,024 threads, 128 KiB); MTTKRP
+// SSYMV items need the panel's row sums in LDS (1,024 threads, 128 KiB, and
+// 32 KiB more for a BF16 request's staged x slice where the device allows
+// 160 KiB per workgroup); MTTKRP
 // items need no LDS and run at full occupancy (256 threads, one kernel per
 // tensor order so that each keeps the registers of its own order); the four
 // waves of an MTTKRP workgroup share an item of a few tiles each.
+template <bool kStageX>
 __global__ __launch_bounds__(kServeBlock) void serve_ssymv_kernel(StepArgs a) {
   extern __shared__ double s_lds[];
   const int i = blockIdx.x;
@@ -108,10 +113,15 @@ __global__ __launch_bounds__(kServeBlock) void serve_ssymv_kernel(StepArgs a) {
   if (r.dtype == SYSTEC_F32)
     ssymv_panel_chunk<float>(dim, H, u.a, u.b, u.c, pcol, prow, pval,
                              static_cast<const float*>(r.in), r.out, s_lds);
-  else
-    ssymv_panel_chunk<uint16_t>(dim, H, u.a, u.b, u.c, pcol, prow, pval,
-                                static_cast<const uint16_t*>(r.in), r.out, s_lds);
+  else  // BF16 x: with kStageX the panel's x slice follows the row sums in LDS
+    ssymv_panel_chunk<uint16_t, kStageX>(dim, H, u.a, u.b, u.c, pcol, prow, pval,
+                                         static_cast<const uint16_t*>(r.in), r.out, s_lds,
+                                         reinterpret_cast<uint16_t*>(s_lds + H));
 }
+
+// Whether the device gives a workgroup room for the staged x slice (set by
+// serve_init_kernels).
+std::atomic<bool> g_serve_stage_x{false};
 
 // One MTTKRP step kernel per (order, input dtype, lane layout, lane class),
 // so that each keeps only the registers of its own variant.
@@ -170,7 +180,12 @@ int launch_serve_step(int kind, int variant, const StepArgs& a, hipStream_t s) {
   const dim3 g(a.nitems);
   hipError_t e = hipSuccess;
   switch (kind) {
-    case 0: serve_ssymv_kernel<<<g, dim3(kServeBlock), kServeLds, s>>>(a); break;  // LDS limit set by serve_init_kernels
+    case 0:  // LDS limits set by serve_init_kernels
+      if (g_serve_stage_x.load(std::memory_order_relaxed))
+        serve_ssymv_kernel<true><<<g, dim3(kServeBlock), kServeLdsStaged, s>>>(a);
+      else
+        serve_ssymv_kernel<false><<<g, dim3(kServeBlock), kServeLds, s>>>(a);
+      break;
     case 3: e = launch_mttkrp_variant<3>(variant, a, g, s); break;
     case 4: e = launch_mttkrp_variant<4>(variant, a, g, s); break;
     default: e = launch_mttkrp_variant<5>(variant, a, g, s); break;
@@ -180,10 +195,23 @@ int launch_serve_step(int kind, int variant, const StepArgs& a, hipStream_t s) {
 }
 
 int serve_init_kernels() {
-  // more than the default 64 KiB of dynamic LDS (set once, before any launch)
-  return check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(serve_ssymv_kernel),
+  // more than the default 64 KiB of dynamic LDS (set before any launch)
+  int dev = 0, limit = 0;
+  int rc = check_hip(hipGetDevice(&dev), "hipGetDevice");
+  if (!rc)
+    rc = check_hip(hipDeviceGetAttribute(&limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev),
+                   "hipDeviceGetAttribute(max shared memory)");
+  if (!rc)
+    rc = check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(serve_ssymv_kernel<false>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, kServeLds),
                    "hipFuncSetAttribute(dynamic LDS)");
+  const bool stage = !rc && limit >= kServeLdsStaged;
+  if (stage)
+    rc = check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(serve_ssymv_kernel<true>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, kServeLdsStaged),
+                   "hipFuncSetAttribute(dynamic LDS)");
+  g_serve_stage_x.store(stage && !rc, std::memory_order_relaxed);
+  return rc;
 }
 
 }  // namespace systec
