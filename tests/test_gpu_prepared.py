@@ -135,6 +135,36 @@ def test_prepared_ssymv_empty_rows_and_panels():
     assert torch.count_nonzero(ye).item() == 0
 
 
+@pytest.mark.parametrize("relabel", [True, False])
+def test_prepared_edge_cases_syprd_and_vertex_order(relabel):
+    """Entries only in the last of nine panels (all in the first panel once
+    relabeled), and a matrix with no entries: SSYMV and SYPRD against the
+    oracle, SYPRD of the empty matrix exactly zero."""
+    import torch
+    n = 140000
+    rowptr = np.zeros(n + 1, dtype=np.int32)
+    rowptr[n - 100:] = np.arange(0, 101, dtype=np.int32)
+    cols = np.arange(n - 100, n, dtype=np.int32)
+    cols[:50] = n - 1  # half of them off the diagonal, all in the last column
+    m = {"n": n, "rowptr": rowptr, "col": cols, "val": synth.dense_uniform(100, seed=5),
+         "x": synth.dense_uniform(n, seed=6)}
+    A = systec.Tensor.from_csr(dev(m["rowptr"]), dev(m["col"]), dev(m["val"].astype(np.float32)),
+                               relabel=relabel)
+    assert (A.vertex_order() is not None) == relabel
+    x, xref = _x(m, "f32")
+    want, _ = oracle.ssymv(n, m["rowptr"], m["col"], f32(m["val"]), xref)
+    assert rel_err(A.ssymv(x).cpu().numpy(), want) <= TOL32
+    s = A.syprd(x).item()
+    want_s, scale, _ = oracle.syprd(n, m["rowptr"], m["col"], f32(m["val"]), xref)
+    assert abs(s - want_s) <= TOL32 * scale
+    A.close()
+    E = systec.Tensor.from_csr(dev(np.zeros(11, np.int32)), torch.empty(0, dtype=torch.int32,
+                               device="cuda"), torch.empty(0, device="cuda"), relabel=relabel)
+    assert E.vertex_order() is None  # nothing to relabel
+    assert E.syprd(dev(np.ones(10, np.float32))).item() == 0.0
+    E.close()
+
+
 def test_prepared_rejects_noncanonical():
     m = synth.ssymv_uniform(300, 5, seed=3)
     col = m["col"].copy()
