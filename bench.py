@@ -329,6 +329,17 @@ def main():
                 out["algos"][name] = {"error": str(e)}
         cfg["algo"] = algo
 
+    # ---- the same call with x and y kept in the stored vertex order ----
+    if a.workload.startswith("ssymv") and a.path == "prepared":
+        perm = A.vertex_order()
+        if perm is not None:
+            xs = x[perm.long()].contiguous()
+            ys = torch.empty_like(y)
+            tsec = timed(lambda: A.ssymv(xs, out=ys, stored_order=True), a.steps, a.warmup)
+            out["stored_order_call"] = {"ms_per_step": tsec * 1e3, "effective_nnz_per_s": eff / tsec,
+                                        "vectors": "in the stored vertex order (no permutations)"}
+            del xs, ys
+
     # ---- the scalar form s = x^T A x on the same matrix (no scattered writes) ----
     if a.workload.startswith("ssymv"):
         sp = torch.empty(1, dtype=torch.float64, device=dev)

@@ -310,6 +310,18 @@ SYSTEC_API int systec_ssymv_t(const systec_tensor* t, const void* x, systec_dtyp
  * scratch of n elements). */
 SYSTEC_API int systec_syprd_t(const systec_tensor* t, const void* x, systec_dtype xdt, double* out,
                               systec_stream stream);
+/* systec_ssymv_t / systec_syprd_t with the vertex order of x and y chosen
+ * by the caller: SYSTEC_ORDER_CALLER (0) is what those calls do;
+ * SYSTEC_ORDER_STORED (1) takes x and returns y in the order the matrix is
+ * stored in (x_stored[i] = x[perm[i]], perm from systec_tensor_vertex_order)
+ * and runs no permutation, for callers such as iterative solvers that keep
+ * their vectors in that order between calls. For a matrix that was not
+ * relabeled both orders are the caller's. Anything else is SYSTEC_EINVAL. */
+enum { SYSTEC_ORDER_CALLER = 0, SYSTEC_ORDER_STORED = 1 };
+SYSTEC_API int systec_ssymv_t_ex(const systec_tensor* t, const void* x, systec_dtype xdt, float* y,
+                                 int vertex_order, systec_stream stream);
+SYSTEC_API int systec_syprd_t_ex(const systec_tensor* t, const void* x, systec_dtype xdt,
+                                 double* out, int vertex_order, systec_stream stream);
 /* C = MTTKRP for a prepared tensor; B, C as for systec_mttkrp. */
 SYSTEC_API int systec_mttkrp_t(const systec_tensor* t, const void* B, systec_dtype bdt,
                                int64_t R, float* C, systec_stream stream);

@@ -316,23 +316,28 @@ class Tensor:
         del keep
         return cls(h)
 
-    def ssymv(self, x, out=None, stream=None):
+    def ssymv(self, x, out=None, stream=None, stored_order=False):
+        """y = A x. stored_order: x and y are in the order the matrix is
+        stored in (see vertex_order), so no permutation runs."""
         torch = _torch()
         _dev(x, None, "x")
         if self.order != 2 or x.numel() != self.dim or (out is not None and out.numel() != self.dim):
             raise ValueError("ssymv needs a prepared matrix and x, y of n elements")
         y = out if out is not None else torch.empty(self.dim, dtype=torch.float32, device=x.device)
-        call("systec_ssymv_t", self._h, _p(x), _dtype_code(x), _p(y), _stream(stream))
+        call("systec_ssymv_t_ex", self._h, _p(x), _dtype_code(x), _p(y), 1 if stored_order else 0,
+             _stream(stream))
         return y
 
-    def syprd(self, x, out=None, stream=None):
-        """x^T A x of the prepared matrix as a float64 device scalar."""
+    def syprd(self, x, out=None, stream=None, stored_order=False):
+        """x^T A x of the prepared matrix as a float64 device scalar
+        (stored_order as for ssymv)."""
         torch = _torch()
         _dev(x, None, "x")
         if self.order != 2 or x.numel() != self.dim:
             raise ValueError("syprd needs a prepared matrix and x of n elements")
         s = out if out is not None else torch.empty(1, dtype=torch.float64, device=x.device)
-        call("systec_syprd_t", self._h, _p(x), _dtype_code(x), _p(s), _stream(stream))
+        call("systec_syprd_t_ex", self._h, _p(x), _dtype_code(x), _p(s), 1 if stored_order else 0,
+             _stream(stream))
         return s
 
     def mttkrp(self, B, out=None, stream=None, algo="auto"):

@@ -52,6 +52,8 @@ SIGNATURES = {
                            ctypes.POINTER(ctypes.c_uint64)],
     "systec_tensor_vertex_order": [P, ctypes.POINTER(ctypes.c_int), P, P],
     "systec_syprd_t": [P, P, I32, P, P],
+    "systec_ssymv_t_ex": [P, P, I32, P, I32, P],
+    "systec_syprd_t_ex": [P, P, I32, P, I32, P],
     "systec_tensor_destroy": [P],
     "systec_ssymv_t": [P, P, I32, P, P],
     "systec_mttkrp_t": [P, P, I32, I64, P, P],

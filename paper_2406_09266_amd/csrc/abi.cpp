@@ -412,6 +412,30 @@ int systec_tensor_info(const systec_tensor* t, int* order, int64_t* dim, int64_t
   return SYSTEC_OK;
 }
 
+int systec_ssymv_t_ex(const systec_tensor* t, const void* x, systec_dtype xdt, float* y,
+                      int vertex_order, systec_stream stream) {
+  if (vertex_order != SYSTEC_ORDER_CALLER && vertex_order != SYSTEC_ORDER_STORED)
+    return fail(SYSTEC_EINVAL, "systec_ssymv_t_ex: vertex_order must be 0 or 1");
+  if (vertex_order == SYSTEC_ORDER_CALLER) return systec_ssymv_t(t, x, xdt, y, stream);
+  if (!t || !t->impl) return fail(SYSTEC_EINVAL, "systec_ssymv_t_ex: NULL handle");
+  if (t->impl->kind != 0) return fail(SYSTEC_EINVAL, "systec_ssymv_t_ex: not a matrix");
+  if (!valid_dtype(xdt)) return fail(SYSTEC_EINVAL, "systec_ssymv_t_ex: unsupported dtype");
+  if (!x || !y) return fail(SYSTEC_EINVAL, "systec_ssymv_t_ex: NULL pointer");
+  return launch_ssymv_panel_stored(t->impl, x, xdt, y, static_cast<hipStream_t>(stream));
+}
+
+int systec_syprd_t_ex(const systec_tensor* t, const void* x, systec_dtype xdt, double* out,
+                      int vertex_order, systec_stream stream) {
+  if (vertex_order != SYSTEC_ORDER_CALLER && vertex_order != SYSTEC_ORDER_STORED)
+    return fail(SYSTEC_EINVAL, "systec_syprd_t_ex: vertex_order must be 0 or 1");
+  if (vertex_order == SYSTEC_ORDER_CALLER) return systec_syprd_t(t, x, xdt, out, stream);
+  if (!t || !t->impl) return fail(SYSTEC_EINVAL, "systec_syprd_t_ex: NULL handle");
+  if (t->impl->kind != 0) return fail(SYSTEC_EINVAL, "systec_syprd_t_ex: not a matrix");
+  if (!valid_dtype(xdt)) return fail(SYSTEC_EINVAL, "systec_syprd_t_ex: unsupported dtype");
+  if (!x || !out) return fail(SYSTEC_EINVAL, "systec_syprd_t_ex: NULL pointer");
+  return launch_syprd_panel_stored(t->impl, x, xdt, out, static_cast<hipStream_t>(stream));
+}
+
 int systec_syprd_t(const systec_tensor* t, const void* x, systec_dtype xdt, double* out,
                    systec_stream stream) {
   if (!t || !t->impl) return fail(SYSTEC_EINVAL, "systec_syprd_t: NULL handle");

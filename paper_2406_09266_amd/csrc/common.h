@@ -141,6 +141,12 @@ int tensor_create_csr(int64_t n, int64_t nnz, const int32_t* rowptr, const int32
 int tensor_create_coo(int order, int64_t I, int64_t nnz, const int32_t* const* idx,
                       const float* val, hipStream_t s, Tensor** out);
 void tensor_free(Tensor* t);
+// The same with x and y (or x alone) already in the matrix's stored vertex
+// order: no permutations.
+int launch_ssymv_panel_stored(const Tensor* t, const void* x, systec_dtype xdt, float* y,
+                              hipStream_t s);
+int launch_syprd_panel_stored(const Tensor* t, const void* x, systec_dtype xdt, double* out,
+                              hipStream_t s);
 // s = x^T A x for a prepared matrix (out: device double[1]).
 int launch_syprd_panel(const Tensor* t, const void* x, systec_dtype xdt, double* out,
                        hipStream_t s);

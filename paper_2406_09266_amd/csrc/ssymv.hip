@@ -516,6 +516,16 @@ int launch_syprd_panel(const Tensor* t, const void* x, systec_dtype xdt, double*
   return rc ? rc : rc2;
 }
 
+int launch_ssymv_panel_stored(const Tensor* t, const void* x, systec_dtype xdt, float* y,
+                              hipStream_t s) {
+  return panel_call(t, x, xdt, y, false, s);
+}
+
+int launch_syprd_panel_stored(const Tensor* t, const void* x, systec_dtype xdt, double* out,
+                              hipStream_t s) {
+  return syprd_panel_call(t, x, xdt, out, s);
+}
+
 int launch_ssymv_panel(const Tensor* t, const void* x, systec_dtype xdt, float* y,
                        hipStream_t s) {
   if (!t->relabeled) return panel_call(t, x, xdt, y, false, s);

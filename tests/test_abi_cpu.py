@@ -54,6 +54,12 @@ def test_invalid_arguments_are_rejected_on_host():
     assert _rc("systec_ssymv", 4, 3, one, null, null, one, 0, one, null) == 1
     # NULL output
     assert _rc("systec_syprd", 4, 3, one, one, one, one, 0, null, null) == 1
+    # vertex order other than caller (0) or stored (1); NULL prepared handle
+    assert _rc("systec_ssymv_t_ex", one, one, 0, one, 7, null) == 1
+    assert _rc("systec_syprd_t_ex", one, one, 0, one, -1, null) == 1
+    assert _rc("systec_ssymv_t_ex", null, one, 0, one, 1, null) == 1
+    assert _rc("systec_syprd_t", null, one, 0, one, null) == 1
+    assert _rc("systec_tensor_vertex_order", null, None, null, null) == 1
     # order out of range (symmetric MTTKRP needs 3..5)
     pp, keep = _lib.ptr_array([16, 16, 16, 16, 16, 16])
     assert _rc("systec_mttkrp", 2, 10, 5, pp, one, one, 0, 4, one, null) == 1

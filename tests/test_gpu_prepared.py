@@ -92,6 +92,28 @@ def test_prepared_syprd(relabel, xdtype):
 
 
 @pytest.mark.parametrize("relabel", [True, False])
+@pytest.mark.parametrize("xdtype", ["f32", "bf16"])
+def test_prepared_stored_order_calls(relabel, xdtype):
+    """x and y in the stored vertex order: the same kernel on the same
+    permuted x, so y_stored equals the caller-order result permuted (up to
+    the order of the FP32 atomic additions), and the scalar, which has no
+    atomics, equals it exactly."""
+    import torch
+    m = synth.ssymv_rmat(scale=14, batch=1 << 16, seed=59)
+    A = systec.Tensor.from_csr(dev(m["rowptr"]), dev(m["col"]), dev(m["val"].astype(np.float32)),
+                               relabel=relabel)
+    x, _ = _x(m, xdtype)
+    perm = A.vertex_order()
+    pl = (perm if perm is not None else torch.arange(m["n"], device="cuda")).long()
+    xs = x[pl].contiguous()
+    y = A.ssymv(x)
+    ys = A.ssymv(xs, stored_order=True)
+    assert rel_err(ys.cpu().numpy(), y[pl].cpu().numpy()) <= TOL32
+    assert A.syprd(xs, stored_order=True).item() == A.syprd(x).item()
+    A.close()
+
+
+@pytest.mark.parametrize("relabel", [True, False])
 def test_prepared_ssymv_reports_vertex_order(relabel):
     """The stored order is a permutation by descending degree, ties in vertex
     order (degree counted on the CPU from the stored triangle)."""
