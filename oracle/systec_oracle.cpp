@@ -33,12 +33,29 @@
 // N!/prod(m!) from the run lengths in integer arithmetic and fails if the two
 // counts differ.
 //
+// Beyond the three kernels above, the oracle defines the kernels built next to
+// them, again as plain definitions over the expanded tensor:
+//      Bellman-Ford  y[i]   = min_j (A[i,j] + d[j])  over stored coordinates
+//                                                              (Sec. 5.2.2)
+//      TTM           C[j,l,r] = sum_k A[k,j,l] B[k,r]          (Sec. 5.2.5)
+//      MTTKRP of a partially symmetric tensor (Sec. 2.1, "Partial Symmetry"):
+//                    the tensor is invariant only under permutations inside
+//                    each part of a partition of its slots, so a stored entry
+//                    stands for every arrangement obtained by permuting each
+//                    part separately (the product of the parts' distinct
+//                    permutations), and C[i,r] = sum T[i,k2..kN] prod_t
+//                    F_{part(t)}[kt,r] with one factor matrix per part.
+//
 // Indices are 0-based (the paper's listings are Julia, 1-based). All values
 // are FP64; FP32 and BF16 inputs convert to FP64 exactly.
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <limits>
+#include <vector>
+
+#include <omp.h>
 
 extern "C" {
 
@@ -115,6 +132,27 @@ int64_t for_each_distinct_permutation(const int32_t* c, int n, F&& f) {
   } while (std::next_permutation(p, p + n));
   if (visited != distinct_perm_count(c, n)) return -1;
   return visited;
+}
+
+// The SSYMV updates of stored rows [i0, i1), added into y; counts accumulate.
+int ssymv_rows(int64_t n, int64_t i0, int64_t i1, const int32_t* rowptr, const int32_t* col,
+               const double* val, const double* x, const uint8_t* row_mask, double* y,
+               oracle_counts* counts) {
+  for (int64_t i = i0; i < i1; ++i) {
+    if (rowptr[i + 1] < rowptr[i]) return ORACLE_EINVAL;
+    for (int64_t q = rowptr[i]; q < rowptr[i + 1]; ++q) {
+      int32_t c[2] = {(int32_t)i, col[q]};
+      if (!prepare_tuple(c, 2, n, counts)) return ORACLE_EINVAL;
+      const double a = val[q];
+      int64_t k = for_each_distinct_permutation(c, 2, [&](const int32_t* p) {
+        if (row_mask && !row_mask[p[0]]) return;
+        y[p[0]] += a * x[p[1]];
+      });
+      if (k < 0) return ORACLE_ECOUNT;
+      counts->effective_nnz += k;
+    }
+  }
+  return ORACLE_OK;
 }
 
 }  // namespace
@@ -194,21 +232,7 @@ int oracle_ssymv(int64_t n, const int32_t* rowptr, const int32_t* col, const dou
   reset(counts);
   std::fill(y, y + n, 0.0);
   if (rowptr[0] != 0) return ORACLE_EINVAL;
-  for (int64_t i = 0; i < n; ++i) {
-    if (rowptr[i + 1] < rowptr[i]) return ORACLE_EINVAL;
-    for (int64_t q = rowptr[i]; q < rowptr[i + 1]; ++q) {
-      int32_t c[2] = {(int32_t)i, col[q]};
-      if (!prepare_tuple(c, 2, n, counts)) return ORACLE_EINVAL;
-      const double a = val[q];
-      int64_t k = for_each_distinct_permutation(c, 2, [&](const int32_t* p) {
-        if (row_mask && !row_mask[p[0]]) return;
-        y[p[0]] += a * x[p[1]];
-      });
-      if (k < 0) return ORACLE_ECOUNT;
-      counts->effective_nnz += k;
-    }
-  }
-  return ORACLE_OK;
+  return ssymv_rows(n, 0, n, rowptr, col, val, x, row_mask, y, counts);
 }
 
 // SYPRD over the expanded matrix (Sec. 5.2.3): s = sum over every distinct
@@ -262,6 +286,248 @@ int oracle_round_bf16(const float* in, double* out, int64_t n) {
     double scaled = std::ldexp(v, -ulp_exp);  // exact: only the exponent changes
     double r = std::nearbyint(scaled);        // default mode: nearest, ties to even
     out[q] = std::ldexp(r, ulp_exp);
+  }
+  return ORACLE_OK;
+}
+
+}  // extern "C"
+
+// ---- all-core variants ----------------------------------------------------
+// The same loops over a static partition of the stored entries into
+// `threads` contiguous ranges: each thread runs the single-threaded oracle on
+// its range into a private FP64 output, and the private outputs are added in
+// thread order, element by element. Deterministic for a fixed thread count;
+// the result differs from the single-threaded one only in the order of FP64
+// additions. Counts are summed. threads <= 0 takes every core OpenMP sees.
+
+namespace {
+
+int resolve_threads(int threads) { return threads > 0 ? threads : omp_get_max_threads(); }
+
+void add_counts(oracle_counts* into, const oracle_counts& k) {
+  into->entries += k.entries;
+  into->effective_nnz += k.effective_nnz;
+  into->noncanonical += k.noncanonical;
+  for (int m = 0; m < 16; ++m) into->hist[m] += k.hist[m];
+}
+
+// out[q] = sum over threads t (in order) of part[t][q], q < len
+void sum_in_thread_order(const std::vector<std::vector<double>>& part, double* out, int64_t len) {
+#pragma omp parallel for schedule(static)
+  for (int64_t q = 0; q < len; ++q) {
+    double s = 0.0;
+    for (const auto& p : part) s += p[q];
+    out[q] = s;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int oracle_mttkrp_mt(int order, int64_t dim, int64_t nnz, const int32_t* idx,
+                     const double* val, int64_t R, const double* B, int out_slot,
+                     const uint8_t* row_mask, double* C, oracle_counts* counts, int threads) {
+  const int T = resolve_threads(threads);
+  if (T <= 1)
+    return oracle_mttkrp(order, dim, nnz, idx, val, R, B, out_slot, row_mask, C, counts);
+  if (order < 1 || order > kMaxOrder || dim < 1 || nnz < 0 || R < 1 || !C || !counts)
+    return ORACLE_EINVAL;
+  std::vector<std::vector<double>> part(T, std::vector<double>(dim * R));
+  std::vector<oracle_counts> kc(T);
+  std::vector<int> rc(T, ORACLE_OK);
+#pragma omp parallel num_threads(T)
+  {
+    const int t = omp_get_thread_num();
+    const int64_t e0 = nnz * t / T, e1 = nnz * (t + 1) / T;
+    rc[t] = oracle_mttkrp(order, dim, e1 - e0, idx + e0 * order, val + e0, R, B, out_slot,
+                          row_mask, part[t].data(), &kc[t]);
+  }
+  reset(counts);
+  for (int t = 0; t < T; ++t) {
+    if (rc[t] != ORACLE_OK) return rc[t];
+    add_counts(counts, kc[t]);
+  }
+  sum_in_thread_order(part, C, dim * R);
+  return ORACLE_OK;
+}
+
+// Rows are split so that each thread gets about nnz / T stored entries.
+int oracle_ssymv_mt(int64_t n, const int32_t* rowptr, const int32_t* col, const double* val,
+                    const double* x, const uint8_t* row_mask, double* y, oracle_counts* counts,
+                    int threads) {
+  const int T = resolve_threads(threads);
+  if (T <= 1) return oracle_ssymv(n, rowptr, col, val, x, row_mask, y, counts);
+  if (n < 1 || !rowptr || !y || !counts || rowptr[0] != 0) return ORACLE_EINVAL;
+  const int64_t nnz = rowptr[n];
+  std::vector<int64_t> r0(T + 1, n);
+  r0[0] = 0;
+  for (int t = 1; t < T; ++t)
+    r0[t] = std::lower_bound(rowptr, rowptr + n + 1, nnz * t / T) - rowptr;
+  std::vector<std::vector<double>> part(T, std::vector<double>(n));
+  std::vector<oracle_counts> kc(T);
+  std::vector<int> rc(T, ORACLE_OK);
+#pragma omp parallel num_threads(T)
+  {
+    const int t = omp_get_thread_num();
+    reset(&kc[t]);
+    rc[t] = ssymv_rows(n, r0[t], r0[t + 1], rowptr, col, val, x, row_mask, part[t].data(), &kc[t]);
+  }
+  reset(counts);
+  for (int t = 0; t < T; ++t) {
+    if (rc[t] != ORACLE_OK) return rc[t];
+    add_counts(counts, kc[t]);
+  }
+  sum_in_thread_order(part, y, n);
+  return ORACLE_OK;
+}
+
+int oracle_threads(void) { return omp_get_max_threads(); }
+
+}  // extern "C"
+
+// ---- kernels beyond SSYMV, SYPRD and MTTKRP ---------------------------------
+
+namespace {
+
+// Visits every arrangement of c obtained by permuting, independently, the
+// slots of each part (parts are consecutive slot ranges start[q] ..
+// start[q] + size[q] - 1, each sorted ascending on entry) and calls f(p).
+template <class F>
+void for_each_part_arrangement(int32_t* p, int q, int nparts, const int* start, const int* size,
+                               int64_t* visited, F& f) {
+  if (q == nparts) {
+    f(p);
+    ++*visited;
+    return;
+  }
+  // std::next_permutation returns false once it has wrapped back to the
+  // ascending order, so the part is left as it was found
+  do {
+    for_each_part_arrangement(p, q + 1, nparts, start, size, visited, f);
+  } while (std::next_permutation(p + start[q], p + start[q] + size[q]));
+}
+
+}  // namespace
+
+extern "C" {
+
+// Bellman-Ford update (Sec. 5.2.2), the (min, +) form of SSYMV: for every
+// distinct permutation p of every stored (i, j, a), y[p1] = min(y[p1],
+// a + d[p2]). Starts from +infinity (the identity of min), so an index with
+// no stored coordinate stays +infinity. Matrix as for oracle_ssymv.
+int oracle_bellman_ford(int64_t n, const int32_t* rowptr, const int32_t* col, const double* val,
+                        const double* d, double* y, oracle_counts* counts) {
+  if (n < 1 || !rowptr || !y || !d || !counts) return ORACLE_EINVAL;
+  reset(counts);
+  std::fill(y, y + n, std::numeric_limits<double>::infinity());
+  if (rowptr[0] != 0) return ORACLE_EINVAL;
+  for (int64_t i = 0; i < n; ++i) {
+    if (rowptr[i + 1] < rowptr[i]) return ORACLE_EINVAL;
+    for (int64_t q = rowptr[i]; q < rowptr[i + 1]; ++q) {
+      int32_t c[2] = {(int32_t)i, col[q]};
+      if (!prepare_tuple(c, 2, n, counts)) return ORACLE_EINVAL;
+      const double a = val[q];
+      int64_t k = for_each_distinct_permutation(c, 2, [&](const int32_t* p) {
+        y[p[0]] = std::min(y[p[0]], a + d[p[1]]);
+      });
+      if (k < 0) return ORACLE_ECOUNT;
+      counts->effective_nnz += k;
+    }
+  }
+  return ORACLE_OK;
+}
+
+// TTM of a fully symmetric 3-index tensor A (Sec. 5.2.5): C[i,j,l] =
+// sum_k A[k,j,l] * B[k,i], with i the column of B (r below). For every
+// distinct permutation p = (k, j, l) of every stored tuple:
+// C[j][l][r] += v * B[k][r]. C is dim x dim x R with r fastest, overwritten.
+int oracle_ttm3(int64_t dim, int64_t nnz, const int32_t* idx, const double* val, int64_t R,
+                const double* B, double* C, oracle_counts* counts) {
+  if (dim < 1 || nnz < 0 || R < 1 || !C || !counts) return ORACLE_EINVAL;
+  reset(counts);
+  std::fill(C, C + dim * dim * R, 0.0);
+  for (int64_t e = 0; e < nnz; ++e) {
+    int32_t c[3];
+    std::memcpy(c, idx + e * 3, sizeof(c));
+    if (!prepare_tuple(c, 3, dim, counts)) return ORACLE_EINVAL;
+    const double v = val[e];
+    int64_t k = for_each_distinct_permutation(c, 3, [&](const int32_t* p) {
+      double* out = C + (static_cast<int64_t>(p[1]) * dim + p[2]) * R;
+      const double* b = B + static_cast<int64_t>(p[0]) * R;
+      for (int64_t r = 0; r < R; ++r) out[r] += v * b[r];
+    });
+    if (k < 0) return ORACLE_ECOUNT;
+    counts->effective_nnz += k;
+  }
+  return ORACLE_OK;
+}
+
+// MTTKRP of a partially symmetric tensor. The slots form nparts consecutive
+// parts of sizes part_size[0..nparts-1] (summing to order); the tensor is
+// symmetric within each part only (Sec. 2.1, Definition "Partial
+// Symmetry"), and a coordinate is canonical when its indices ascend inside
+// every part (Definition "Canonical"). F holds one dim x R factor matrix per
+// part (F + q*dim*R). For every arrangement p of every stored tuple (each
+// part permuted on its own, distinct arrangements only):
+//   C[p_1][r] += v * prod_{t >= 2} F_{part(t)}[p_t][r]
+// (the output is mode 1, in part 0). A tuple whose part does not ascend is
+// sorted inside that part (same orbit) and counted as non-canonical. The
+// visited count must equal the product of the parts' N_q!/prod(m!) counts.
+// hist records the equality pattern of slots adjacent inside one part.
+int oracle_mttkrp_partial(int order, int nparts, const int32_t* part_size, int64_t dim,
+                          int64_t nnz, const int32_t* idx, const double* val, int64_t R,
+                          const double* F, double* C, oracle_counts* counts) {
+  if (order < 1 || order > kMaxOrder || nparts < 1 || nparts > order || !part_size || dim < 1 ||
+      nnz < 0 || R < 1 || !F || !C || !counts)
+    return ORACLE_EINVAL;
+  int start[kMaxOrder], size[kMaxOrder], part_of[kMaxOrder];
+  int sum = 0;
+  for (int q = 0; q < nparts; ++q) {
+    if (part_size[q] < 1) return ORACLE_EINVAL;
+    start[q] = sum;
+    size[q] = part_size[q];
+    for (int t = sum; t < sum + size[q] && t < kMaxOrder; ++t) part_of[t] = q;
+    sum += size[q];
+  }
+  if (sum != order) return ORACLE_EINVAL;
+  reset(counts);
+  std::fill(C, C + dim * R, 0.0);
+  for (int64_t e = 0; e < nnz; ++e) {
+    int32_t c[kMaxOrder];
+    std::memcpy(c, idx + e * order, sizeof(int32_t) * order);
+    bool canonical = true;
+    for (int t = 0; t < order; ++t)
+      if (c[t] < 0 || c[t] >= dim) return ORACLE_EINVAL;
+    for (int q = 0; q < nparts; ++q) {
+      for (int t = start[q] + 1; t < start[q] + size[q]; ++t)
+        if (c[t - 1] > c[t]) canonical = false;
+      std::sort(c + start[q], c + start[q] + size[q]);
+    }
+    if (!canonical) counts->noncanonical += 1;
+    int pattern = 0;
+    for (int t = 0; t + 1 < order; ++t)
+      if (part_of[t] == part_of[t + 1] && c[t] == c[t + 1]) pattern |= 1 << t;
+    counts->hist[pattern] += 1;
+    counts->entries += 1;
+    int64_t expected = 1;
+    for (int q = 0; q < nparts; ++q) expected *= distinct_perm_count(c + start[q], size[q]);
+    const double v = val[e];
+    int32_t p[kMaxOrder];
+    std::memcpy(p, c, sizeof(int32_t) * order);
+    int64_t visited = 0;
+    auto update = [&](const int32_t* a) {
+      double* crow = C + static_cast<int64_t>(a[0]) * R;
+      for (int64_t r = 0; r < R; ++r) {
+        double prod = v;
+        for (int t = 1; t < order; ++t)
+          prod *= F[(static_cast<int64_t>(part_of[t]) * dim + a[t]) * R + r];
+        crow[r] += prod;
+      }
+    };
+    for_each_part_arrangement(p, 0, nparts, start, size, &visited, update);
+    if (visited != expected) return ORACLE_ECOUNT;
+    counts->effective_nnz += visited;
   }
   return ORACLE_OK;
 }

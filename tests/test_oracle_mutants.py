@@ -3,7 +3,9 @@
 Each case plants one mistake in a copy of the oracle's source (on the CPU),
 builds it, and runs the pin suite against the mutant in a subprocess: the
 suite has to fail. This shows that a dropped term, a wrong index, a transposed
-operand, a wrong multiplicity or a wrong rounding cannot slip through.
+operand, a wrong multiplicity or a wrong rounding cannot slip through, in the
+three original kernels and in the Bellman-Ford, TTM and partial-symmetry
+definitions.
 """
 import os
 import subprocess
@@ -27,6 +29,17 @@ MUTANTS = {
     "syprd_sign": ("acc += term;", "acc -= term;"),
     "bf16_ties_away": ("std::nearbyint(scaled)", "std::round(scaled)"),
     "bf16_truncates": ("std::nearbyint(scaled)", "std::trunc(scaled)"),
+    "bellman_ford_transposed_operand": ("a + d[p[1]]", "a + d[p[0]]"),
+    "bellman_ford_max_instead_of_min": ("std::min(y[p[0]], a + d[p[1]])",
+                                        "std::max(y[p[0]], a + d[p[1]])"),
+    "ttm_contracts_an_output_slot": ("const double* b = B + static_cast<int64_t>(p[0]) * R;",
+                                     "const double* b = B + static_cast<int64_t>(p[1]) * R;"),
+    "partial_permutes_first_part_only": (
+        "} while (std::next_permutation(p + start[q], p + start[q] + size[q]));",
+        "} while (q == 0 && std::next_permutation(p + start[q], p + start[q] + size[q]));"),
+    "partial_one_factor_for_every_part": (
+        "prod *= F[(static_cast<int64_t>(part_of[t]) * dim + a[t]) * R + r];",
+        "prod *= F[(static_cast<int64_t>(0) * dim + a[t]) * R + r];"),
 }
 
 
@@ -38,10 +51,11 @@ def test_pins_reject_mutant(name, tmp_path):
     mutant = tmp_path / "mutant.cpp"
     mutant.write_text(src.replace(old, new))
     lib = tmp_path / "libmutant.so"
-    subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-o", str(lib),
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-fopenmp", "-shared", "-o", str(lib),
                            str(mutant)])
     env = dict(os.environ, SYSTEC_ORACLE_LIB=str(lib))
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_next_pins.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=300)
     assert r.returncode != 0, f"pins did not catch mutant {name}:\n{r.stdout[-2000:]}"

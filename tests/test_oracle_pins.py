@@ -388,3 +388,33 @@ def test_round_bf16_matches_torch_conversion():
     ours = oracle.round_bf16(x)
     ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float64).numpy()
     np.testing.assert_array_equal(ours, ref)
+
+
+# ----------------------------------------------------- all-core variants ----
+
+@pytest.mark.parametrize("threads", [2, 3, 0])
+def test_all_core_oracle_equals_single_thread(threads):
+    """The all-core oracle (static partition of the stored entries, private
+    FP64 outputs added in thread order) gives the single-threaded result: bit
+    for bit with integer-valued inputs (every partial sum is exact), and with
+    the same counts. It adds nothing of its own to the definition."""
+    t = synth.sym_coo(4, 30, 4000, 0.3, seed=71)
+    v = synth.integer_valued(t["val"].size, seed=72).astype(np.float64)
+    B = synth.integer_valued((30, 6), seed=73)
+    C1, k1 = oracle.mttkrp(4, 30, t["idx"].T, v, B)
+    Ct, kt = oracle.mttkrp(4, 30, t["idx"].T, v, B, threads=threads)
+    np.testing.assert_array_equal(Ct, C1)
+    assert kt == k1
+    m = synth.ssymv_uniform(701, 9, seed=74)
+    a = synth.integer_valued(m["col"].size, seed=75).astype(np.float64)
+    x = synth.integer_valued(701, seed=76).astype(np.float64)
+    y1, c1 = oracle.ssymv(701, m["rowptr"], m["col"], a, x)
+    yt, ct = oracle.ssymv(701, m["rowptr"], m["col"], a, x, threads=threads)
+    np.testing.assert_array_equal(yt, y1)
+    assert ct == c1
+    # and a dense brute force for the same matrix
+    A = np.zeros((701, 701))
+    rows = np.repeat(np.arange(701), np.diff(m["rowptr"]))
+    A[rows, m["col"]] = a
+    A[m["col"], rows] = a
+    np.testing.assert_array_equal(yt, A @ x)
