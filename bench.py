@@ -8,17 +8,28 @@ input: output zeroing plus the symmetric kernel over the canonical entries.
 Inputs are resident in HBM before the timed region starts. The metric is
 effective nnz/s: the number of entries of the fully expanded (non-symmetric)
 tensor, sum over stored entries of N!/prod(m!), divided by the time of a
-step. The JSON line also carries the roofline of the dominant kernel (its
-own duration from HIP events around its launch, on its stream), the same
-call on the non-symmetric comparison kernel, and the FP64 CPU oracle timed
-on this host (one core) on the same workload, with the error of the GPU
-result against it.
+step. The headline workload (default: the R-MAT SSYMV) fills the top level of
+the one JSON line; every workload named by --also (default: the 3-D and 5-D
+MTTKRP) is measured in the same run and reported in a record of its own with
+the same fields. Each record carries:
+  value, ms_per_step   warm steps, the K timed ones
+  cold                 min/median of single calls after a 512 MiB cache flush
+  roofline             algorithmic bytes / the dominant kernel's own time
+                       (HIP events around its launches, on its stream), as a
+                       fraction of the 8 TB/s peak and of a measured device
+                       copy; traffic from the committed rocprofv3 counters
+  nonsymmetric         the same call on the expanded operand
+  oracle_rel_err       against the FP64 oracle on the values the GPU saw
+  e2e_rel_err          against the FP64 oracle on the original FP64 inputs
+  cpu_baseline         the oracle on every host core (its all-core variant),
+  cpu_baseline_1core   and on one core
 
 Workloads (synthetic, seeded; shaped like the paper's):
   ssymv_rmat   (default) R-MAT scale 22, n=4,194,304, avg degree 16, upper CSR
   ssymv_small  n=2,000, ~10 stored entries per row
   mttkrp3      order 3, I=100,000, 20M canonical entries, R=32
   mttkrp5      order 5, I=5,000, 5M canonical entries, R=16
+  served_mix   Poisson arrivals against resident tensors (its own JSON line)
 """
 from __future__ import annotations
 
@@ -75,7 +86,10 @@ def parse():
                          "of its timings); oneshot: the canonical CSR/COO as given")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline leg")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle legs")
+    ap.add_argument("--also", default="mttkrp3,mttkrp5",
+                    help="further workloads measured in the same run, each reported in a "
+                         "record of its own in the same JSON line ('' for none)")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the non-symmetric comparison kernel")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -195,6 +209,295 @@ def kernel_ms(fn, reps):
     return kt.total_ms / max(1, kt.launches), kt.launches
 
 
+def _progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cold_ms(torch, fn, reps, flush):
+    """Times `reps` calls one by one with events on the current stream, each
+    after a write of `flush` (512 MiB, twice the last-level cache) that is not
+    timed. Returns min and median in ms."""
+    torch.cuda.synchronize()
+    evs = []
+    for _ in range(reps):
+        flush.fill_(0.0)
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        fn()
+        e.record()
+        evs.append((s, e))
+    torch.cuda.synchronize()
+    ts = sorted(s.elapsed_time(e) for s, e in evs)
+    return {"ms_min": ts[0], "ms_median": ts[len(ts) // 2], "reps": reps,
+            "flush_bytes": flush.numel() * 4}
+
+
+def copy_ceiling_gbs(torch, dev):
+    """Read + write bandwidth of a plain 1 GiB device copy (the measured
+    streaming ceiling beside the 8 TB/s peak)."""
+    src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    src.fill_(1.0)
+    for _ in range(2):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e.record()
+    torch.cuda.synchronize()
+    gbs = 5 * 2 * src.numel() * 4 / (s.elapsed_time(e) * 1e-3) / 1e9
+    del src, dst
+    return round(gbs, 1)
+
+
+def rel(got, want):
+    return float(np.linalg.norm(got - want) / max(np.linalg.norm(want), 1e-300))
+
+
+def roofline(b_alg, k_ms, kernel_key, kernel_src, traffic_key, copy_gbs):
+    achieved = b_alg / (k_ms * 1e-3) / 1e9
+    h = src_hash(*kernel_src)
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": load_traffic(traffic_key, h, b_alg),
+            "kernel": kernel_key, "kernel_ms": k_ms, "kernel_source_hash": h,
+            "copy_ceiling_gbs": copy_gbs, "frac_of_copy_ceiling": round(achieved / copy_gbs, 4)}
+
+
+def measure_ssymv(a, torch, systec, w, dev, flush, copy_gbs, with_cpu):
+    """The SSYMV workload: the prepared call (the step), its kernel, cold
+    times, the one-shot call, the stored-order call, SYPRD, the non-symmetric
+    comparisons, the errors against the oracle and the oracle's own time."""
+    n, U = w["n"], w["col"].size
+    rp = torch.from_numpy(w["rowptr"]).to(dev)
+    col = torch.from_numpy(w["col"]).to(dev)
+    val = torch.from_numpy(w["val"].astype(np.float32)).to(dev)
+    x32 = torch.from_numpy(w["x"].astype(np.float32)).to(dev)
+    x = systec.quantize_bf16(x32) if a.form == "bf16" else x32
+    y = torch.empty(n, dtype=torch.float32, device=dev)
+    rows = torch.repeat_interleave(torch.arange(n, dtype=torch.int32, device=dev), rp[1:] - rp[:-1])
+    hist, eff = systec.expansion_stats([rows, col], n)
+    del rows
+    sx = 2 if a.form == "bf16" else 4
+    b_alg = 4 * (n + 1) + 8 * U + n * sx + 4 * n
+    t_prep = time.perf_counter()
+    relabel = {"auto": None, "on": True, "off": False}[a.relabel]
+    A = systec.Tensor.from_csr(rp, col, val, relabel=relabel)
+    torch.cuda.synchronize()
+    t_prep = time.perf_counter() - t_prep
+    prepared = lambda: A.ssymv(x, out=y)  # noqa: E731
+    oneshot = lambda: systec.ssymv(rp, col, val, x, out=y)  # noqa: E731
+    step, other = (prepared, oneshot) if a.path == "prepared" else (oneshot, prepared)
+    kernel_key = "ssymv_panel" if a.path == "prepared" else "ssymv"
+    kernel_src = ("ssymv.hip", "panel_device.h", "wave_ops.h", "plan.hip")
+    rec = {"config": {"workload": a.workload, "n": n, "stored_nnz": U, "effective_nnz": eff,
+                      "diagonal_nnz": hist[1], "x_storage": a.form, "accumulate": "f32",
+                      "vertex_order": a.relabel, "relabeled": A.vertex_order() is not None,
+                      "path": a.path, "B_alg_bytes": b_alg}}
+    _progress("ssymv: timed region")
+    sec = timed(step, a.steps, a.warmup)
+    rec["value"] = eff / sec
+    rec["ms_per_step"] = sec * 1e3
+    rec["config"]["canonical_nnz_per_s"] = U / sec
+    k_ms, _ = kernel_ms(step, max(10, a.steps))
+    rec["roofline"] = roofline(b_alg, k_ms, kernel_key, kernel_src,
+                               f"{kernel_key}:{a.workload}:{a.form}", copy_gbs)
+    rec["cold"] = cold_ms(torch, step, 20, flush)
+    osec = timed(other, max(5, a.steps // 4), 2)
+    rec["other_path"] = {"path": "oneshot" if a.path == "prepared" else "prepared",
+                         "ms_per_step": osec * 1e3, "effective_nnz_per_s": eff / osec}
+    perm = A.vertex_order()
+    if perm is not None and a.path == "prepared":
+        xs = x[perm.long()].contiguous()
+        ys = torch.empty_like(y)
+        tsec = timed(lambda: A.ssymv(xs, out=ys, stored_order=True), a.steps, a.warmup)
+        rec["stored_order_call"] = {"ms_per_step": tsec * 1e3, "effective_nnz_per_s": eff / tsec,
+                                    "vectors": "in the stored vertex order (no permutations)"}
+        del xs, ys
+    # the scalar form s = x^T A x (no scattered writes)
+    sp = torch.empty(1, dtype=torch.float64, device=dev)
+    s_alg = 4 * (n + 1) + 8 * U + n * sx
+    rec["syprd"] = {"B_alg_bytes": s_alg}
+    for name, fn in (("prepared", lambda: A.syprd(x, out=sp)),
+                     ("oneshot", lambda: systec.syprd(rp, col, val, x, out=sp))):
+        ssec = timed(fn, a.steps, a.warmup)
+        rec["syprd"][name] = {"ms_per_step": ssec * 1e3, "effective_nnz_per_s": eff / ssec,
+                              "hbm_frac_alg": round(s_alg / ssec / 1e9 / HBM_PEAK_GBS, 4)}
+    if not a.no_compare:
+        _progress("ssymv: non-symmetric comparison")
+        try:
+            orders = {"vertex": (rp, col, val, x)}
+            if perm is not None:
+                rp2, col2, val2 = degree_ordered_csr(torch, rp, col, val, perm)
+                orders["degree"] = (rp2, col2, val2, x[perm.long()].contiguous())
+            same = "degree" if perm is not None else "vertex"
+            yf = torch.empty_like(y)
+            forms, full = {}, {}
+            for name, (r_, c_, v_, x_) in orders.items():
+                full[name] = systec.expand_csr(r_, c_, v_) + (x_,)
+                frp, fcol, fval, xo = full[name]
+                forms[name] = timed(lambda: systec.spmv_csr(frp, fcol, fval, xo, out=yf),  # noqa: E731
+                                    a.steps, a.warmup)
+            csec = forms[same]
+            rec["nonsymmetric"] = {"ms_per_step": csec * 1e3, "effective_nnz_per_s": eff / csec,
+                                   "speedup_symmetric": csec / sec, "vertex_order": same,
+                                   "ms_by_vertex_order": {k: v * 1e3 for k, v in forms.items()}}
+            try:
+                rs = {}
+                for name, (frp, fcol, fval, xo) in full.items():
+                    rs[name], _ = rocsparse_spmv(torch, frp, fcol, fval, xo.float(), a.steps, a.warmup)
+                rec["rocsparse_general_spmv"] = {
+                    "alg": "adaptive", "x_dtype": "f32",
+                    "ms_by_vertex_order": {k: v * 1e3 for k, v in rs.items()},
+                    "speedup_symmetric_vs_best": min(rs.values()) / sec}
+            except Exception as e:  # report, do not hide
+                rec["rocsparse_general_spmv"] = {"error": str(e)}
+            del full, orders
+        except Exception as e:  # report, do not hide
+            rec["nonsymmetric"] = {"error": str(e)}
+    # errors of the timed call's result against the oracle: on the values
+    # the GPU saw (kernel check) and on the original FP64 inputs (end to end)
+    import oracle
+    step()
+    torch.cuda.synchronize()
+    got = y.cpu().numpy().astype(np.float64)
+    xref = x.to(torch.float64).cpu().numpy()
+    vref = w["val"].astype(np.float32).astype(np.float64)
+    t0 = time.perf_counter()
+    want, _ = oracle.ssymv(n, w["rowptr"], w["col"], vref, xref, threads=0)
+    t_all = time.perf_counter() - t0
+    e2e, _ = oracle.ssymv(n, w["rowptr"], w["col"], w["val"], w["x"], threads=0)
+    rec["oracle_rel_err"] = rel(got, want)
+    rec["e2e_rel_err"] = rel(got, e2e)
+    if with_cpu:
+        rec.update(cpu_legs(lambda th: oracle.ssymv(n, w["rowptr"], w["col"], vref, xref,
+                                                    threads=th),
+                            eff, a.cpu_seconds, t_all, "the whole workload"))
+    rec["setup_s"] = {"prepare_operand": round(t_prep, 3)}
+    A.close()
+    return rec
+
+
+def cpu_legs(call, work, seconds, t_first, what):
+    """The oracle timed on this host: every core (its all-core variant, the
+    reported baseline) and one core, each repeated for about seconds / 2."""
+    import oracle
+    out = {}
+    for label, th in (("cpu_baseline", 0), ("cpu_baseline_1core", 1)):
+        reps, t = 0, 0.0
+        while (t < seconds / 2 and reps < 20) or reps == 0:
+            t0 = time.perf_counter()
+            call(th)
+            t += time.perf_counter() - t0
+            reps += 1
+        out[label] = {"value": work * reps / t, "unit": "effective nnz/s",
+                      "cores": oracle.threads() if th == 0 else 1, "kind": "oracle",
+                      "sample": f"{what}, {reps} oracle call(s), {t:.1f} s",
+                      "host_cpu": _cpu_model(), "host_nproc": os.cpu_count()}
+    return out
+
+
+def measure_mttkrp(a, torch, systec, w, name, dev, flush, copy_gbs, with_cpu, steps, warmup):
+    """One MTTKRP workload: the prepared call (slot views; the step), its
+    kernel, cold times, every algorithm, the one-shot call, the non-symmetric
+    kernel on the expanded tensor, errors against the oracle on every element
+    and the oracle's own time."""
+    order, I = w["order"], w["dim"]
+    R = w["B"].shape[1]
+    nnz = w["val"].size
+    idx = [torch.from_numpy(v).to(dev) for v in w["idx"]]
+    val = torch.from_numpy(w["val"].astype(np.float32)).to(dev)
+    B32 = torch.from_numpy(w["B"].astype(np.float32)).to(dev)
+    B = systec.quantize_bf16(B32) if a.form == "bf16" else B32
+    C = torch.empty((I, R), dtype=torch.float32, device=dev)
+    hist, eff = systec.expansion_stats(idx, I)
+    sb = 2 if a.form == "bf16" else 4
+    # compulsory bytes with a pointer over the leading index: pointer + other
+    # indices + values + factor read once + output written once
+    b_alg = 4 * (I + 1) + nnz * (4 * (order - 1) + 4) + I * R * sb + 4 * I * R
+    algo = a.algo
+    if algo == "auto":
+        algo = systec.mttkrp_choose(I, R, a.form == "bf16", a.path == "prepared")
+    t_prep = time.perf_counter()
+    T = systec.Tensor.from_coo(idx, val, I)
+    torch.cuda.synchronize()
+    t_prep = time.perf_counter() - t_prep
+    prepared = lambda: T.mttkrp(B, out=C, algo=algo)  # noqa: E731
+    oneshot = lambda: systec.mttkrp(idx, val, B, out=C, algo="atomic")  # noqa: E731
+    step, other = (prepared, oneshot) if a.path == "prepared" else (oneshot, prepared)
+    kernel_key = f"mttkrp{order}_{algo}" + ("" if a.path == "prepared" else "_oneshot")
+    kernel_src = {"views": ("mttkrp.hip", "mttkrp_device.h", "plan.hip"),
+                  "atomic": ("mttkrp.hip", "mttkrp_device.h"),
+                  "lds": ("mttkrp_lds.hip", "mttkrp_device.h", "plan.hip")}[algo]
+    rec = {"config": {"workload": name, "order": order, "I": I, "R": R, "stored_nnz": nnz,
+                      "effective_nnz": eff, "pattern_hist": hist, "B_storage": a.form,
+                      "accumulate": "f32", "path": a.path, "algo": algo, "B_alg_bytes": b_alg}}
+    _progress(f"{name}: timed region")
+    sec = timed(step, steps, warmup)
+    rec["value"] = eff / sec
+    rec["unit"] = "effective nnz/s"
+    rec["ms_per_step"] = sec * 1e3
+    rec["config"]["canonical_nnz_per_s"] = nnz / sec
+    k_ms, _ = kernel_ms(step, max(10, steps))
+    rec["roofline"] = roofline(b_alg, k_ms, kernel_key, kernel_src,
+                               f"{kernel_key}:{name}:{a.form}", copy_gbs)
+    rec["cold"] = cold_ms(torch, step, 20, flush)
+    osec = timed(other, max(5, steps // 4), 2)
+    rec["other_path"] = {"path": "oneshot" if a.path == "prepared" else "prepared",
+                         "ms_per_step": osec * 1e3, "effective_nnz_per_s": eff / osec}
+    rec["algos"] = {}
+    for alg in ("views", "atomic", "lds"):
+        try:
+            asec = timed(lambda: T.mttkrp(B, out=C, algo=alg), max(5, steps // 2), 2)  # noqa: E731
+            rec["algos"][alg] = {"ms_per_step": asec * 1e3, "effective_nnz_per_s": eff / asec}
+        except Exception as e:  # not applicable to this shape
+            rec["algos"][alg] = {"error": str(e)}
+    if not a.no_compare:
+        _progress(f"{name}: non-symmetric comparison")
+        try:
+            fidx, fval = systec.expand_coo(idx, val, I)
+            Cf = torch.empty_like(C)
+            csec = timed(lambda: systec.mttkrp_full(fidx, fval, B, out=Cf), steps, warmup)  # noqa: E731
+            rec["nonsymmetric"] = {"ms_per_step": csec * 1e3, "effective_nnz_per_s": eff / csec,
+                                   "speedup_symmetric": csec / sec,
+                                   "expanded_entries": int(fval.numel())}
+            del fidx, fval, Cf
+            torch.cuda.empty_cache()
+        except Exception as e:  # report, do not hide
+            rec["nonsymmetric"] = {"error": str(e)}
+    import oracle
+    step()
+    torch.cuda.synchronize()
+    got = C.cpu().numpy().astype(np.float64)
+    Bref = B.to(torch.float64).cpu().numpy()
+    vref = w["val"].astype(np.float32).astype(np.float64)
+    t0 = time.perf_counter()
+    want, _ = oracle.mttkrp(order, I, w["idx"].T, vref, Bref, threads=0)
+    t_all = time.perf_counter() - t0
+    e2e, _ = oracle.mttkrp(order, I, w["idx"].T, w["val"], w["B"], threads=0)
+    rec["oracle_rel_err"] = rel(got, want)
+    rec["e2e_rel_err"] = rel(got, e2e)
+    if with_cpu:
+        # the whole workload on every core; one core on the first k stored
+        # entries, about the same time
+        legs = cpu_legs(lambda th: oracle.mttkrp(order, I, w["idx"].T, vref, Bref, threads=th),
+                        eff, a.cpu_seconds / 2, t_all, "the whole workload")
+        rec["cpu_baseline"] = legs["cpu_baseline"]
+        k = int(min(nnz, max(1000, nnz * a.cpu_seconds / 4 / max(t_all * oracle.threads(), 1e-3))))
+        t0 = time.perf_counter()
+        _, cnt = oracle.mttkrp(order, I, w["idx"][:, :k].T, vref[:k], Bref, threads=1)
+        t1 = time.perf_counter() - t0
+        rec["cpu_baseline_1core"] = {
+            "value": cnt["effective_nnz"] / t1, "unit": "effective nnz/s", "cores": 1,
+            "kind": "oracle", "sample": f"first {k} of {nnz} stored entries "
+                                        f"({cnt['effective_nnz']} expanded), {t1:.1f} s",
+            "host_cpu": _cpu_model(), "host_nproc": os.cpu_count()}
+    rec["setup_s"] = {"prepare_operand": round(t_prep, 3)}
+    T.close()
+    return rec
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -213,71 +516,6 @@ def main():
     if a.workload == "served_mix":
         served_mix(a, torch, systec, synth, dev)
         return
-    t_gen = time.perf_counter()
-    w = synth.workload(a.workload)
-    t_gen = time.perf_counter() - t_gen
-    out = {"metric": "sym sparse MTTKRP/SSYMV effective nnz/s + %HBM peak",
-           "unit": "effective nnz/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-           "data": "synthetic (seeded generators; no dataset)"}
-
-    if a.workload.startswith("ssymv"):
-        n, U = w["n"], w["col"].size
-        rp = torch.from_numpy(w["rowptr"]).to(dev)
-        col = torch.from_numpy(w["col"]).to(dev)
-        val = torch.from_numpy(w["val"].astype(np.float32)).to(dev)
-        x32 = torch.from_numpy(w["x"].astype(np.float32)).to(dev)
-        x = systec.quantize_bf16(x32) if a.form == "bf16" else x32
-        y = torch.empty(n, dtype=torch.float32, device=dev)
-        rows = torch.repeat_interleave(torch.arange(n, dtype=torch.int32, device=dev),
-                                       rp[1:] - rp[:-1])
-        hist, eff = systec.expansion_stats([rows, col], n)
-        del rows
-        sx = 2 if a.form == "bf16" else 4
-        b_alg = 4 * (n + 1) + 8 * U + n * sx + 4 * n
-        oneshot = lambda: systec.ssymv(rp, col, val, x, out=y)  # noqa: E731
-        t_prep = time.perf_counter()
-        relabel = {"auto": None, "on": True, "off": False}[a.relabel]
-        A = systec.Tensor.from_csr(rp, col, val, relabel=relabel)
-        t_prep = time.perf_counter() - t_prep
-        prepared = lambda: A.ssymv(x, out=y)  # noqa: E731
-        kernel_key = "ssymv_panel" if a.path == "prepared" else "ssymv"
-        kernel_src = ("ssymv.hip", "panel_device.h", "wave_ops.h", "plan.hip")
-        cfg = {"workload": a.workload, "n": n, "stored_nnz": U, "effective_nnz": eff,
-               "diagonal_nnz": hist[1], "x_storage": a.form, "accumulate": "f32",
-               "vertex_order": a.relabel}
-    else:
-        order, I = w["order"], w["dim"]
-        R = w["B"].shape[1]
-        nnz = w["val"].size
-        idx = [torch.from_numpy(v).to(dev) for v in w["idx"]]
-        val = torch.from_numpy(w["val"].astype(np.float32)).to(dev)
-        B32 = torch.from_numpy(w["B"].astype(np.float32)).to(dev)
-        B = systec.quantize_bf16(B32) if a.form == "bf16" else B32
-        C = torch.empty((I, R), dtype=torch.float32, device=dev)
-        hist, eff = systec.expansion_stats(idx, I)
-        sb = 2 if a.form == "bf16" else 4
-        # compulsory bytes with a pointer over the leading index (the leading
-        # index need not be streamed): pointer + other indices + values +
-        # factor read once + output written once
-        b_alg = 4 * (I + 1) + nnz * (4 * (order - 1) + 4) + I * R * sb + 4 * I * R
-        algo = a.algo
-        if algo == "auto":
-            algo = systec.mttkrp_choose(I, R, a.form == "bf16", a.path == "prepared")
-        oneshot_algo = "atomic"
-        oneshot = lambda: systec.mttkrp(idx, val, B, out=C, algo=oneshot_algo)  # noqa: E731
-        t_prep = time.perf_counter()
-        T = systec.Tensor.from_coo(idx, val, I)
-        t_prep = time.perf_counter() - t_prep
-        prepared = lambda: T.mttkrp(B, out=C, algo=algo)  # noqa: E731
-        kernel_key = f"mttkrp{order}_{algo}" + ("" if a.path == "prepared" else "_oneshot")
-        kernel_src = {"views": ("mttkrp.hip", "mttkrp_device.h", "plan.hip"),
-                      "atomic": ("mttkrp.hip", "mttkrp_device.h"),
-                      "lds": ("mttkrp_lds.hip", "mttkrp_device.h", "plan.hip")}[algo]
-        cfg = {"workload": a.workload, "order": order, "I": I, "R": R, "stored_nnz": nnz,
-               "effective_nnz": eff, "pattern_hist": hist, "B_storage": a.form,
-               "accumulate": "f32"}
-
     if a.copy_calibration:
         # a plain device copy of known size, its source pushed out of the
         # last-level cache first, so that FETCH_SIZE/WRITE_SIZE of its
@@ -285,171 +523,44 @@ def main():
         src = torch.empty(a.copy_calibration << 18, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         src.fill_(1.0)
-        flush = torch.empty(1 << 28, dtype=torch.float32, device=dev)
-        flush.fill_(0.0)
+        fl = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        fl.fill_(0.0)
         torch.cuda.synchronize()
         dst.copy_(src)
         torch.cuda.synchronize()
-        del src, dst, flush
-
-    step, other = (prepared, oneshot) if a.path == "prepared" else (oneshot, prepared)
-    cfg["path"] = a.path
-
-    # ---- timed region: K steps, synchronized on both sides ----
-    sec = timed(step, a.steps, a.warmup)
-    ms_step = sec * 1e3
-    out["value"] = eff / sec
-    out["ms_per_step"] = ms_step
-    cfg["canonical_nnz_per_s"] = cfg["stored_nnz"] / sec
-    cfg["B_alg_bytes"] = b_alg
-    out["config"] = cfg
-
-    # ---- dominant kernel: its own launches, HIP events on its stream ----
-    k_ms, launches = kernel_ms(step, max(10, a.steps))
-    achieved = b_alg / (k_ms * 1e-3) / 1e9
-    h = src_hash(*kernel_src)
-    traffic = load_traffic(f"{kernel_key}:{a.workload}:{a.form}", h, b_alg)
-    osec = timed(other, max(5, a.steps // 4), 2)
-    out["other_path"] = {"path": "oneshot" if a.path == "prepared" else "prepared",
-                         "ms_per_step": osec * 1e3, "effective_nnz_per_s": eff / osec}
-    out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                       "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                       "traffic": traffic, "kernel": kernel_key, "kernel_ms": k_ms,
-                       "kernel_source_hash": h}
-
-    # ---- every MTTKRP algorithm on the same prepared tensor ----
-    if not a.workload.startswith("ssymv"):
-        out["algos"] = {}
-        for name in ("views", "atomic", "lds"):
-            try:
-                fn = lambda: T.mttkrp(B, out=C, algo=name)  # noqa: E731
-                asec = timed(fn, max(5, a.steps // 2), 2)
-                out["algos"][name] = {"ms_per_step": asec * 1e3, "effective_nnz_per_s": eff / asec}
-            except Exception as e:  # not applicable to this shape
-                out["algos"][name] = {"error": str(e)}
-        cfg["algo"] = algo
-
-    # ---- the same call with x and y kept in the stored vertex order ----
-    if a.workload.startswith("ssymv") and a.path == "prepared":
-        perm = A.vertex_order()
-        if perm is not None:
-            xs = x[perm.long()].contiguous()
-            ys = torch.empty_like(y)
-            tsec = timed(lambda: A.ssymv(xs, out=ys, stored_order=True), a.steps, a.warmup)
-            out["stored_order_call"] = {"ms_per_step": tsec * 1e3, "effective_nnz_per_s": eff / tsec,
-                                        "vectors": "in the stored vertex order (no permutations)"}
-            del xs, ys
-
-    # ---- the scalar form s = x^T A x on the same matrix (no scattered writes) ----
+        del src, dst, fl
+    flush = torch.empty(1 << 27, dtype=torch.float32, device=dev)  # 512 MiB
+    copy_gbs = copy_ceiling_gbs(torch, dev)
+    with_cpu = not a.no_cpu
+    t_gen = time.perf_counter()
+    w = synth.workload(a.workload)
+    t_gen = time.perf_counter() - t_gen
+    out = {"metric": "sym sparse MTTKRP/SSYMV effective nnz/s + %HBM peak",
+           "unit": "effective nnz/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": a.form, "data": "synthetic (seeded generators; no dataset)"}
     if a.workload.startswith("ssymv"):
-        sp = torch.empty(1, dtype=torch.float64, device=dev)
-        s_alg = 4 * (n + 1) + 8 * U + n * sx
-        out["syprd"] = {"B_alg_bytes": s_alg}
-        for name, fn in (("prepared", lambda: A.syprd(x, out=sp)),
-                         ("oneshot", lambda: systec.syprd(rp, col, val, x, out=sp))):
-            ssec = timed(fn, a.steps, a.warmup)
-            out["syprd"][name] = {"ms_per_step": ssec * 1e3, "effective_nnz_per_s": eff / ssec,
-                                  "hbm_frac_alg": round(s_alg / ssec / 1e9 / HBM_PEAK_GBS, 4)}
-
-    # ---- the non-symmetric comparison kernel on the expanded operand ----
-    if not a.no_compare:
-        try:
-            if a.workload.startswith("ssymv"):
-                # the full matrix in the order the symmetric path stores it,
-                # and in the caller's order
-                perm = A.vertex_order()
-                orders = {"vertex": (rp, col, val, x)}
-                if perm is not None:
-                    rp2, col2, val2 = degree_ordered_csr(torch, rp, col, val, perm)
-                    orders["degree"] = (rp2, col2, val2, x[perm.long()].contiguous())
-                same = "degree" if perm is not None else "vertex"
-                yf = torch.empty_like(y)
-                forms, full = {}, {}
-                for name, (r_, c_, v_, x_) in orders.items():
-                    full[name] = systec.expand_csr(r_, c_, v_) + (x_,)
-                    frp, fcol, fval, xo = full[name]
-                    forms[name] = timed(lambda: systec.spmv_csr(frp, fcol, fval, xo, out=yf),  # noqa: E731
-                                        a.steps, a.warmup)
-                csec = forms[same]
-                out["nonsymmetric"] = {"ms_per_step": csec * 1e3, "effective_nnz_per_s": eff / csec,
-                                       "speedup_symmetric": csec / sec, "vertex_order": same,
-                                       "ms_by_vertex_order": {k: v * 1e3 for k, v in forms.items()}}
-                # an outside reference: rocSPARSE's general SpMV (adaptive,
-                # FP32 x holding the same values) on the same full matrices
-                try:
-                    rs, diffs = {}, {}
-                    for name, (frp, fcol, fval, xo) in full.items():
-                        rsec, yr = rocsparse_spmv(torch, frp, fcol, fval, xo.float(), a.steps, a.warmup)
-                        rs[name] = rsec
-                        if name == "vertex":
-                            prepared()
-                            torch.cuda.synchronize()
-                            diffs[name] = (torch.linalg.norm(yr - y) / torch.linalg.norm(y)).item()
-                    best = min(rs.values())
-                    out["rocsparse_general_spmv"] = {
-                        "alg": "adaptive", "x_dtype": "f32", "ms_by_vertex_order": {k: v * 1e3 for k, v in rs.items()},
-                        "rel_diff_vs_symmetric": diffs, "speedup_symmetric_vs_best": best / sec}
-                except Exception as e:  # report, do not hide
-                    out["rocsparse_general_spmv"] = {"error": str(e)}
-                del full, orders
-            else:
-                fidx, fval = systec.expand_coo(idx, val, I)
-                Cf = torch.empty_like(C)
-                cstep = lambda: systec.mttkrp_full(fidx, fval, B, out=Cf)  # noqa: E731
-                csec = timed(cstep, a.steps, a.warmup)
-                out["nonsymmetric"] = {"ms_per_step": csec * 1e3, "effective_nnz_per_s": eff / csec,
-                                       "speedup_symmetric": csec / sec}
-                del cstep
-        except Exception as e:  # report, do not hide
-            out["nonsymmetric"] = {"error": str(e)}
-
-    # ---- CPU oracle leg (rank 0, one core), and the error of the GPU result ----
-    if not a.no_cpu:
-        import oracle
-        torch.cuda.synchronize()
-        if a.workload.startswith("ssymv"):
-            step()
-            got = y.cpu().numpy().astype(np.float64)
-            xref = (x.to(torch.float64).cpu().numpy())
-            vref = w["val"].astype(np.float32).astype(np.float64)
-            reps, t_cpu = 0, 0.0
-            while t_cpu < a.cpu_seconds and reps < 20:
-                t0 = time.perf_counter()
-                want, _ = oracle.ssymv(n, w["rowptr"], w["col"], vref, xref)
-                t_cpu += time.perf_counter() - t0
-                reps += 1
-            sample = f"the whole workload, {reps} oracle call(s)"
-            work = eff * reps
-        else:
-            step()
-            got = C.cpu().numpy().astype(np.float64)
-            Bref = B.to(torch.float64).cpu().numpy()
-            vref = w["val"].astype(np.float32).astype(np.float64)
-            # bounded sample: the first k stored entries (all of their expanded
-            # updates), sized to about cpu_seconds of oracle work
-            k = min(nnz, 200_000)
-            t0 = time.perf_counter()
-            oracle.mttkrp(order, I, w["idx"][:, :k].T, vref[:k], Bref)
-            t1 = time.perf_counter() - t0
-            k = int(min(nnz, max(k, k * a.cpu_seconds / max(t1, 1e-3))))
-            t0 = time.perf_counter()
-            _, cnt = oracle.mttkrp(order, I, w["idx"][:, :k].T, vref[:k], Bref)
-            t_cpu = time.perf_counter() - t0
-            work = cnt["effective_nnz"]
-            sample = f"first {k} of {nnz} stored entries ({work} expanded)"
-            # error on sampled output rows (full oracle restricted to them)
-            rng = np.random.Generator(np.random.PCG64(0))
-            rows_s = np.unique(rng.integers(0, I, 256))
-            mask = np.zeros(I, np.uint8)
-            mask[rows_s] = 1
-            want_full, _ = oracle.mttkrp(order, I, w["idx"].T, vref, Bref, row_mask=mask)
-            got, want = got[rows_s], want_full[rows_s]
-        err = float(np.linalg.norm(got - want) / max(np.linalg.norm(want), 1e-300))
-        out["cpu_baseline"] = {"value": work / t_cpu, "unit": "effective nnz/s", "cores": 1,
-                               "kind": "oracle", "sample": sample,
-                               "host_cpu": _cpu_model(), "host_nproc": os.cpu_count()}
-        out["oracle_rel_err"] = err
-    out["setup_s"] = {"generate": round(t_gen, 2), "prepare_operand": round(t_prep, 3)}
+        rec = measure_ssymv(a, torch, systec, w, dev, flush, copy_gbs, with_cpu)
+    else:
+        rec = measure_mttkrp(a, torch, systec, w, a.workload, dev, flush, copy_gbs, with_cpu,
+                             a.steps, a.warmup)
+    rec.pop("unit", None)
+    rec["setup_s"]["generate"] = round(t_gen, 2)
+    out.update(rec)
+    del w
+    # the other workloads, each in its own record of the same line
+    subs = [s for s in a.also.split(",") if s and s != a.workload]
+    for name in subs:
+        _progress(f"{name}: generate")
+        t_gen = time.perf_counter()
+        ws = synth.workload(name)
+        t_gen = time.perf_counter() - t_gen
+        r = measure_mttkrp(a, torch, systec, ws, name, dev, flush, copy_gbs, with_cpu,
+                           max(10, a.steps), a.warmup)
+        r["dtype"] = a.form
+        r["setup_s"]["generate"] = round(t_gen, 2)
+        out[name] = r
+        del ws
     print(json.dumps(out), flush=True)
 
 

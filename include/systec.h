@@ -104,6 +104,25 @@ SYSTEC_API int systec_syprd(int64_t n, int64_t nnz, const int32_t* rowptr, const
                  systec_stream stream);
 
 /* ------------------------------------------------------------------------
+ * Bellman-Ford update  y[i] = min_j (A[i,j] + d[j])  (Sec. 5.2.2: A the
+ * symmetric matrix of edge lengths, d the path lengths after k steps, y
+ * after k + 1; the (min, +) form of SSYMV). The minimum runs over the
+ * coordinates the full symmetric matrix stores: a stored a = A[i,j], i < j,
+ * offers y[i] the value a + d[j] and y[j] the value a + d[i]; a diagonal one
+ * offers y[i] the value a + d[i]. An index with no stored coordinate gets
+ * +inf (the identity of min); to carry d[i] over, store a zero diagonal.
+ * A as for systec_ssymv (stored values are the edge lengths, FP32);
+ *   d       device float[n], finite or +inf
+ *   y       device float[n], overwritten.
+ * Each y[i] is the FP32 sum a + d of its minimizing coordinate, independent
+ * of the order of the updates (the minima are taken exactly, on integer keys
+ * that order like the values). Errors: EINVAL, EDEVICE.
+ * ---------------------------------------------------------------------- */
+SYSTEC_API int systec_bellman_ford(int64_t n, int64_t nnz, const int32_t* rowptr,
+                                   const int32_t* col, const float* val, const float* d,
+                                   float* y, systec_stream stream);
+
+/* ------------------------------------------------------------------------
  * Symmetric MTTKRP of order N = 3, 4, 5 (Sec. 5.2.6):
  *   C[i,r] = sum_{k2..kN} T[i,k2,..,kN] * B[k2,r] * ... * B[kN,r]
  * T is fully symmetric, given by its canonical entries in COO, structure of
@@ -124,6 +143,46 @@ SYSTEC_API int systec_syprd(int64_t n, int64_t nnz, const int32_t* rowptr, const
 SYSTEC_API int systec_mttkrp(int order, int64_t I, int64_t nnz, const int32_t* const* idx,
                   const float* val, const void* B, systec_dtype bdt, int64_t R, float* C,
                   systec_stream stream);
+
+/* ------------------------------------------------------------------------
+ * TTM with visible output symmetry (Sec. 5.2.5; Sec. 3.2.1, visible output
+ * symmetry): for a fully symmetric 3-index tensor T,
+ *   C[j, l, r] = sum_k T[k, j, l] B[k, r]
+ * T as canonical COO of order 3 (as for systec_mttkrp); B device I x R
+ * (F32 or BF16); C device float I x I x R, row-major (r fastest), dense.
+ * C is symmetric in (j, l): the call computes its canonical half, j <= l,
+ * from the stored entries (an entry updates C[j, l, :] += v B[k, :] once per
+ * distinct value k of its tuple, with (j, l) the other two indices in
+ * ascending order) and, if mirror == 1, copies it to the other half (the
+ * paper's post-processing loop); with mirror == 0 the entries with j > l are
+ * left untouched. The canonical half is overwritten.
+ * I >= 1, 1 <= R, I * R < 2^31, I * I * R < 2^40. Errors: EINVAL, EDEVICE.
+ * ---------------------------------------------------------------------- */
+SYSTEC_API int systec_ttm(int64_t I, int64_t nnz, const int32_t* const* idx, const float* val,
+                          const void* B, systec_dtype bdt, int64_t R, float* C, int mirror,
+                          systec_stream stream);
+
+/* ------------------------------------------------------------------------
+ * MTTKRP of a partially symmetric tensor (Sec. 2.1, "Partial Symmetry"):
+ * the `order` slots form `nparts` consecutive parts of sizes part_sizes[q]
+ * (host int32[nparts], summing to order); the tensor is invariant under
+ * permutations inside each part only and is given by its canonical entries
+ * (indices ascending inside every part; the list sorted lexicographically).
+ * Each part q has a factor matrix F[q] (host array of nparts device
+ * pointers, each I x R of dtype fdt), and
+ *   C[i, r] = sum T[i, k2, .., kN] prod_{t >= 2} F[part(t)][k_t, r]
+ * (output mode 1, in part 0). An entry updates, for each slot t of part 0
+ * that starts a run of equal indices, C[c_t, :] += coef * v * prod_{s != t}
+ * F[part(s)][c_s, :], coef = (arrangements of part 0) * (run length) /
+ * (size of part 0) * prod over the other parts of their arrangements. One
+ * part of size `order` is the fully symmetric MTTKRP.
+ *   C       device float I x R, overwritten.
+ * order in {2..5}, I >= 1, R >= 1, I*R < 2^31. Errors: EINVAL, EDEVICE.
+ * ---------------------------------------------------------------------- */
+SYSTEC_API int systec_mttkrp_partial(int order, int nparts, const int32_t* part_sizes, int64_t I,
+                                     int64_t nnz, const int32_t* const* idx, const float* val,
+                                     const void* const* F, systec_dtype fdt, int64_t R,
+                                     float* C, systec_stream stream);
 
 /* ------------------------------------------------------------------------
  * How the updates of the non-leading slots are resolved (all give the same
@@ -263,8 +322,12 @@ SYSTEC_API int systec_quantize_bf16(const float* in, uint16_t* out, int64_t n, s
  * caller's buffers may be freed after create returns. Create validates the
  * canonical form on the device (SYSTEC_ENONCANON if it does not hold),
  * synchronizes `stream`, and returns SYSTEC_ENOMEM if the copy does not fit.
- * The handle may be used from any stream of the device it was created on;
- * calls that share a handle only read it.
+ * The handle may be used from any stream of the device it was created on.
+ * The handle holds the work buffers its calls need (SYPRD's per-chunk
+ * partials; for a relabeled matrix the input and output in the stored
+ * order), so no call allocates; calls that use them and share the handle
+ * are ordered on the device (each waits for the previous one's work, on
+ * whatever stream it ran).
  * ---------------------------------------------------------------------- */
 typedef struct systec_tensor systec_tensor;
 
@@ -277,7 +340,8 @@ SYSTEC_API int systec_tensor_create_csr(int64_t n, int64_t nnz, const int32_t* r
  * high-degree vertices then share panels and columns, and the column-side
  * updates of systec_ssymv_t merge into fewer cache lines; each call then
  * permutes x in and y out (two gathers of n elements, inside the call, on
- * its stream, with stream-ordered scratch). relabel = 0 keeps the order
+ * its stream, through two n-element work vectors that the handle holds, so
+ * that a call allocates nothing). relabel = 0 keeps the order
  * (what systec_tensor_create_csr does); relabel = -1 relabels when the
  * largest degree exceeds 8 times the mean (power-law graphs). Anything else
  * is SYSTEC_EINVAL. A server serves a relabeled matrix too: each of its
@@ -293,6 +357,9 @@ SYSTEC_API int systec_tensor_create_coo(int order, int64_t I, int64_t nnz,
  * the expanded tensor), device bytes held. Any output pointer may be NULL. */
 SYSTEC_API int systec_tensor_info(const systec_tensor* t, int* order, int64_t* dim,
                                   int64_t* nnz, int64_t* effective_nnz, uint64_t* bytes);
+/* The device bytes a prepared operand holds (what systec_serve_register
+ * charges against the budget). Errors: EINVAL (NULL argument). */
+SYSTEC_API int systec_tensor_bytes(const systec_tensor* t, uint64_t* bytes);
 /* The vertex order a prepared matrix is stored in. *relabeled (may be NULL)
  * is 1 if systec_tensor_create_csr_ex relabeled it, else 0. If perm is not
  * NULL and the matrix was relabeled, perm (device int32[n], caller-owned)
@@ -306,8 +373,8 @@ SYSTEC_API int systec_ssymv_t(const systec_tensor* t, const void* x, systec_dtyp
                               systec_stream stream);
 /* s = x^T A x for a prepared matrix; x and out as for systec_syprd (one
  * FP32 partial per chunk of the prepared format, FP64 final sum). A matrix
- * stored with its vertices relabeled permutes x in first (stream-ordered
- * scratch of n elements). */
+ * stored with its vertices relabeled permutes x in first (into the handle's
+ * work vector). */
 SYSTEC_API int systec_syprd_t(const systec_tensor* t, const void* x, systec_dtype xdt, double* out,
                               systec_stream stream);
 /* systec_ssymv_t / systec_syprd_t with the vertex order of x and y chosen
@@ -322,9 +389,37 @@ SYSTEC_API int systec_ssymv_t_ex(const systec_tensor* t, const void* x, systec_d
                                  int vertex_order, systec_stream stream);
 SYSTEC_API int systec_syprd_t_ex(const systec_tensor* t, const void* x, systec_dtype xdt,
                                  double* out, int vertex_order, systec_stream stream);
+/* The Bellman-Ford update for a prepared matrix; d and y as for
+ * systec_bellman_ford (in the caller's vertex order; a relabeled matrix
+ * permutes d in and y out through the handle's work vectors). */
+SYSTEC_API int systec_bellman_ford_t(const systec_tensor* t, const float* d, float* y,
+                                     systec_stream stream);
 /* C = MTTKRP for a prepared tensor; B, C as for systec_mttkrp. */
 SYSTEC_API int systec_mttkrp_t(const systec_tensor* t, const void* B, systec_dtype bdt,
                                int64_t R, float* C, systec_stream stream);
+/* ------------------------------------------------------------------------
+ * One step of symmetric CP-ALS around MTTKRP (Sec. 5.2.6: a symmetric CP
+ * decomposition models T by one factor matrix B, T ~ [[B]] = sum_r b_r (x)
+ * ... (x) b_r, so the least-squares update is the same in every mode):
+ *   C      = MTTKRP(T, B)                  (as systec_mttkrp_t, slot views)
+ *   G      = B^T B                         (R x R)
+ *   B_new  = C (G^(N-1))^-1                (elementwise power; Cholesky)
+ *   fit    = { ||T||^2, <T, [[B]]>, ||[[B]]||^2, ||T - [[B]]||^2 }
+ * with ||T||^2 = sum over stored entries of (distinct permutations) v^2,
+ * <T,[[B]]> = sum C .* B and ||[[B]]||^2 = sum G.^N.
+ *   t       a prepared tensor of order 3..5
+ *   B       device I x R row-major, dtype bdt (F32 or BF16); 1 <= R <= 64
+ *   C       device float I x R (the MTTKRP), overwritten
+ *   B_new   device float I x R, overwritten
+ *   G       device float R x R, overwritten
+ *   fit     device double[4], overwritten (FP32 partial sums, FP64 final)
+ * If G^(N-1) is not positive definite (B without full column rank) B_new
+ * is NaN. Stream-ordered workspace of about 2 KiB * R^2 is taken and
+ * returned inside the call. Errors: EINVAL, EDEVICE.
+ * ---------------------------------------------------------------------- */
+SYSTEC_API int systec_cp_step(const systec_tensor* t, const void* B, systec_dtype bdt,
+                              int64_t R, float* C, float* B_new, float* G, double* fit,
+                              systec_stream stream);
 /* systec_mttkrp_t with an explicit algorithm (systec_mttkrp_t is AUTO: the
  * slot views).
  * ATOMIC runs on the tensor's canonical list (its first view). */
@@ -388,9 +483,20 @@ typedef struct {
 SYSTEC_API int systec_serve_create(const systec_serve_config* cfg, systec_server** out);
 SYSTEC_API int systec_serve_register(systec_server* s, systec_tensor* t, int64_t* tensor_id);
 SYSTEC_API int systec_serve_unregister(systec_server* s, int64_t tensor_id);
+/* The server's streams do not wait for the caller's: `in` must hold its
+ * values and `out` must be free of earlier work when systec_serve_submit is
+ * called (for example after synchronizing the stream that wrote them).
+ * systec_serve_submit_after orders the request after the work enqueued on
+ * the caller's stream `after` so far instead: the server's stream waits on
+ * the device for that work before it zeroes `out` and reads `in`, and the
+ * caller need not synchronize (torch: after = current_stream). */
 SYSTEC_API int systec_serve_submit(systec_server* s, int64_t tensor_id, const void* in,
                                    systec_dtype dt, int64_t R, float* out, int64_t arrival_ns,
                                    int64_t* req_id);
+SYSTEC_API int systec_serve_submit_after(systec_server* s, int64_t tensor_id, const void* in,
+                                         systec_dtype dt, int64_t R, float* out,
+                                         int64_t arrival_ns, systec_stream after,
+                                         int64_t* req_id);
 /* state: 0 queued, 1 running, 2 done, 3 failed */
 SYSTEC_API int systec_serve_poll(systec_server* s, int64_t req_id, int* state);
 /* timeout_us < 0 waits without limit; SYSTEC_ETIMEOUT when it expires */

@@ -21,7 +21,7 @@ from . import _lib
 from ._lib import SYSTEC_BF16, SYSTEC_F32, SystecError, call, ptr_array
 
 __all__ = [
-    "SystecError", "ssymv", "syprd", "mttkrp", "spmv_csr", "mttkrp_full", "expand_csr",
+    "SystecError", "ssymv", "syprd", "bellman_ford", "mttkrp", "ttm", "mttkrp_partial", "spmv_csr", "mttkrp_full", "expand_csr",
     "expand_coo", "expansion_stats", "validate_csr_upper", "validate_coo",
     "canonicalize_coo", "quantize_bf16", "KernelTimer", "version", "Tensor", "Server",
 ]
@@ -104,6 +104,23 @@ def syprd(rowptr, col, val, x, out=None, stream=None):
     return s
 
 
+def bellman_ford(rowptr, col, val, d, out=None, stream=None):
+    """y[i] = min_j (A[i,j] + d[j]) over the stored coordinates of the
+    symmetric matrix A (upper-triangle CSR; float32 edge lengths and
+    distances); +inf where row i stores nothing."""
+    torch = _torch()
+    n = rowptr.numel() - 1
+    _dev(rowptr, torch.int32, "rowptr"), _dev(col, torch.int32, "col")
+    _dev(val, torch.float32, "val"), _dev(d, torch.float32, "d")
+    if d.numel() != n:
+        raise ValueError("d must have n elements")
+    y = out if out is not None else torch.empty(n, dtype=torch.float32, device=d.device)
+    _dev(y, torch.float32, "out")
+    call("systec_bellman_ford", n, col.numel(), _p(rowptr), _p(col), _p(val), _p(d), _p(y),
+         _stream(stream))
+    return y
+
+
 # --------------------------------------------------------------- MTTKRP ----
 
 def _idx_ptrs(idx, name="idx"):
@@ -150,6 +167,55 @@ def mttkrp(idx, val, B, out=None, stream=None, algo="auto"):
     call("systec_mttkrp_ex", order, I, val.numel(), pp, _p(val), _p(B), _dtype_code(B), R, _p(C),
          _algo(algo), _stream(stream))
     del keep
+    return C
+
+
+def ttm(idx, val, B, out=None, mirror=True, stream=None):
+    """TTM of a fully symmetric 3-index tensor (canonical COO: three int32
+    index tensors, float32 val) with B (I x R, float32 or bfloat16):
+    C[j, l, r] = sum_k T[k, j, l] B[k, r], an I x I x R float32 tensor,
+    symmetric in (j, l). The canonical half j <= l is computed; mirror=False
+    leaves the other half unwritten."""
+    torch = _torch()
+    if len(idx) != 3:
+        raise ValueError("ttm needs a 3-index tensor")
+    I, R = B.shape
+    _dev(B, None, "B"), _dev(val, torch.float32, "val")
+    C = out if out is not None else torch.empty((I, I, R), dtype=torch.float32, device=B.device)
+    _dev(C, torch.float32, "out")
+    if tuple(C.shape) != (I, I, R):
+        raise ValueError("out must be I x I x R")
+    pp, keep = _idx_ptrs(idx)
+    call("systec_ttm", I, val.numel(), pp, _p(val), _p(B), _dtype_code(B), R, _p(C),
+         1 if mirror else 0, _stream(stream))
+    del keep
+    return C
+
+
+def mttkrp_partial(parts, idx, val, F, out=None, stream=None):
+    """MTTKRP (output mode 1) of a tensor symmetric only inside consecutive
+    parts of its slots: parts lists the part sizes (e.g. [2, 2]), idx the
+    canonical COO (indices ascending inside each part), F one I x R factor
+    per part (float32 or bfloat16, all of one dtype)."""
+    import numpy as np
+    torch = _torch()
+    order = len(idx)
+    if sum(parts) != order or len(F) != len(parts):
+        raise ValueError("parts must sum to the order and give one factor per part")
+    I, R = F[0].shape
+    for f in F:
+        _dev(f, F[0].dtype, "F")
+        if tuple(f.shape) != (I, R):
+            raise ValueError("every factor must be I x R")
+    _dev(val, torch.float32, "val")
+    C = out if out is not None else torch.empty((I, R), dtype=torch.float32, device=val.device)
+    _dev(C, torch.float32, "out")
+    sizes = np.ascontiguousarray(parts, dtype=np.int32)
+    pp, keep = _idx_ptrs(idx)
+    fp, fkeep = ptr_array([f.data_ptr() for f in F])
+    call("systec_mttkrp_partial", order, len(parts), ctypes.c_void_p(sizes.ctypes.data), I,
+         val.numel(), pp, _p(val), fp, _dtype_code(F[0]), R, _p(C), _stream(stream))
+    del keep, fkeep
     return C
 
 
@@ -340,6 +406,17 @@ class Tensor:
              _stream(stream))
         return s
 
+    def bellman_ford(self, d, out=None, stream=None):
+        """y[i] = min_j (A[i,j] + d[j]) for the prepared matrix (float32 d)."""
+        torch = _torch()
+        _dev(d, torch.float32, "d")
+        if self.order != 2 or d.numel() != self.dim:
+            raise ValueError("bellman_ford needs a prepared matrix and d of n elements")
+        y = out if out is not None else torch.empty(self.dim, dtype=torch.float32, device=d.device)
+        _dev(y, torch.float32, "out")
+        call("systec_bellman_ford_t", self._h, _p(d), _p(y), _stream(stream))
+        return y
+
     def mttkrp(self, B, out=None, stream=None, algo="auto"):
         """C = MTTKRP of the prepared tensor; algo: "auto", "views" (slot
         views), "lds" (slot views with B staged in LDS; small index spaces)
@@ -356,6 +433,24 @@ class Tensor:
         call("systec_mttkrp_t_ex", self._h, _p(B), _dtype_code(B), R, _p(C), _algo(algo),
              _stream(stream))
         return C
+
+    def cp_step(self, B, stream=None):
+        """One symmetric CP-ALS step around this tensor's MTTKRP: returns
+        (B_new, C, G, fit) with C = MTTKRP(T, B), G = B^T B, B_new = C
+        (G^(N-1))^-1 and fit a float64 device tensor of ||T||^2,
+        <T,[[B]]>, ||[[B]]||^2 and ||T - [[B]]||^2."""
+        torch = _torch()
+        _dev(B, None, "B")
+        I, R = B.shape
+        if I != self.dim or self.order < 3:
+            raise ValueError("B must have one row per tensor index")
+        C = torch.empty((I, R), dtype=torch.float32, device=B.device)
+        B_new = torch.empty((I, R), dtype=torch.float32, device=B.device)
+        G = torch.empty((R, R), dtype=torch.float32, device=B.device)
+        fit = torch.empty(4, dtype=torch.float64, device=B.device)
+        call("systec_cp_step", self._h, _p(B), _dtype_code(B), R, _p(C), _p(B_new), _p(G),
+             _p(fit), _stream(stream))
+        return B_new, C, G, fit
 
     def close(self):
         if self._h is not None and self._h.value:
@@ -413,7 +508,10 @@ class Server:
         self._kind[tid.value] = (tensor.order, tensor.dim, tensor.effective_nnz)
         return tid.value
 
-    def submit(self, tensor_id, inp, out, arrival_ns=0):
+    def submit(self, tensor_id, inp, out, arrival_ns=0, stream=None):
+        """Queues out = A inp (or C = MTTKRP(T, B)). The request's work on the
+        device starts after the work enqueued so far on `stream` (default:
+        the current stream), which wrote inp or last used out."""
         torch = _torch()
         _dev(inp, None, "input"), _dev(out, torch.float32, "output")
         R = 1 if inp.dim() == 1 else inp.shape[1]
@@ -425,8 +523,8 @@ class Server:
             if inp.dim() != 2 or inp.shape[0] != dim or tuple(out.shape) != (dim, R):
                 raise ValueError("B must be I x R and C I x R")
         rid = ctypes.c_int64()
-        call("systec_serve_submit", self._h, tensor_id, _p(inp), _dtype_code(inp), R, _p(out),
-             int(arrival_ns), ctypes.byref(rid))
+        call("systec_serve_submit_after", self._h, tensor_id, _p(inp), _dtype_code(inp), R,
+             _p(out), int(arrival_ns), _stream(stream), ctypes.byref(rid))
         self._live[rid.value] = (inp, out)
         return rid.value
 

@@ -31,6 +31,11 @@ SIGNATURES = {
     "systec_version": [],
     "systec_ssymv": [I64, I64, P, P, P, P, I32, P, P],
     "systec_syprd": [I64, I64, P, P, P, P, I32, P, P],
+    "systec_bellman_ford": [I64, I64, P, P, P, P, P, P],
+    "systec_bellman_ford_t": [P, P, P, P],
+    "systec_cp_step": [P, P, I32, I64, P, P, P, P, P],
+    "systec_ttm": [I64, I64, PP, P, P, I32, I64, P, I32, P],
+    "systec_mttkrp_partial": [I32, I32, P, I64, I64, PP, P, PP, I32, I64, P, P],
     "systec_mttkrp": [I32, I64, I64, PP, P, P, I32, I64, P, P],
     "systec_mttkrp_choose": [I64, I32, I64, I32, P],
     "systec_mttkrp_ex": [I32, I64, I64, PP, P, P, I32, I64, P, I32, P],
@@ -51,6 +56,7 @@ SIGNATURES = {
     "systec_tensor_info": [P, ctypes.POINTER(ctypes.c_int), PI64, PI64, PI64,
                            ctypes.POINTER(ctypes.c_uint64)],
     "systec_tensor_vertex_order": [P, ctypes.POINTER(ctypes.c_int), P, P],
+    "systec_tensor_bytes": [P, ctypes.POINTER(ctypes.c_uint64)],
     "systec_syprd_t": [P, P, I32, P, P],
     "systec_ssymv_t_ex": [P, P, I32, P, I32, P],
     "systec_syprd_t_ex": [P, P, I32, P, I32, P],
@@ -83,6 +89,7 @@ SIGNATURES.update({
     "systec_serve_register": [P, P, PI64],
     "systec_serve_unregister": [P, I64],
     "systec_serve_submit": [P, I64, P, I32, I64, P, I64, PI64],
+    "systec_serve_submit_after": [P, I64, P, I32, I64, P, I64, P, PI64],
     "systec_serve_poll": [P, I64, ctypes.POINTER(ctypes.c_int)],
     "systec_serve_wait": [P, I64, I64],
     "systec_serve_get_stats": [P, ctypes.POINTER(ServeStats)],

@@ -21,8 +21,9 @@ INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(PKG, "libsystec.so")
 BUILD_DIR = os.path.join(ROOT, "_build", "systec")
 
-SOURCES = ["abi.cpp", "ssymv.hip", "mttkrp.hip", "mttkrp_lds.hip", "aux.hip", "plan.hip", "serve.cpp",
-           "serve_kernel.hip"]
+SOURCES = ["abi.cpp", "ssymv.hip", "bellman.hip", "mttkrp.hip", "mttkrp_lds.hip", "aux.hip",
+           "plan.hip", "serve.cpp", "serve_kernel.hip", "cp.hip", "ttm.hip",
+           "mttkrp_partial.hip"]
 
 ARCH = "gfx950"
 COMMON_FLAGS = [

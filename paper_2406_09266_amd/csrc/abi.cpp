@@ -464,6 +464,73 @@ int systec_tensor_destroy(systec_tensor* t) {
   return SYSTEC_OK;
 }
 
+int systec_bellman_ford(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col,
+                        const float* val, const float* d, float* y, systec_stream stream) {
+  int rc = check_csr_args("systec_bellman_ford", n, nnz, rowptr, col, val, d, SYSTEC_F32, y);
+  if (rc) return rc;
+  auto s = static_cast<hipStream_t>(stream);
+  if (validate_always() && (rc = systec_validate_csr_upper(n, nnz, rowptr, col, stream))) return rc;
+  return launch_bellman_ford(n, nnz, rowptr, col, val, d, y, s);
+}
+
+int systec_bellman_ford_t(const systec_tensor* t, const float* d, float* y,
+                          systec_stream stream) {
+  if (!t || !t->impl) return fail(SYSTEC_EINVAL, "systec_bellman_ford_t: NULL handle");
+  if (t->impl->kind != 0) return fail(SYSTEC_EINVAL, "systec_bellman_ford_t: not a matrix");
+  if (!d || !y) return fail(SYSTEC_EINVAL, "systec_bellman_ford_t: NULL pointer");
+  return launch_bellman_ford_panel(t->impl, d, y, static_cast<hipStream_t>(stream));
+}
+
+int systec_ttm(int64_t I, int64_t nnz, const int32_t* const* idx, const float* val,
+               const void* B, systec_dtype bdt, int64_t R, float* C, int mirror,
+               systec_stream stream) {
+  int rc = check_coo_args("systec_ttm", 3, 3, I, nnz, idx, val);
+  if (rc) return rc;
+  if (R < 1 || R > kMaxIndex) return fail(SYSTEC_EINVAL, "systec_ttm: R out of range");
+  if (I * R > kMaxIndex) return fail(SYSTEC_EINVAL, "systec_ttm: I*R too large");
+  if (I > (int64_t(1) << 40) / (I * R)) return fail(SYSTEC_EINVAL, "systec_ttm: I*I*R too large");
+  if (!valid_dtype(bdt)) return fail(SYSTEC_EINVAL, "systec_ttm: unsupported dtype");
+  if (!B || !C) return fail(SYSTEC_EINVAL, "systec_ttm: NULL pointer");
+  if (mirror != 0 && mirror != 1) return fail(SYSTEC_EINVAL, "systec_ttm: mirror must be 0 or 1");
+  auto s = static_cast<hipStream_t>(stream);
+  if (validate_always() && (rc = systec_validate_coo(3, I, nnz, idx, stream))) return rc;
+  return launch_ttm(I, nnz, idx, val, B, bdt, R, C, mirror == 1, s);
+}
+
+int systec_mttkrp_partial(int order, int nparts, const int32_t* part_sizes, int64_t I,
+                          int64_t nnz, const int32_t* const* idx, const float* val,
+                          const void* const* F, systec_dtype fdt, int64_t R, float* C,
+                          systec_stream stream) {
+  int rc = check_coo_args("systec_mttkrp_partial", order, 2, I, nnz, idx, val);
+  if (rc) return rc;
+  if (!part_sizes || nparts < 1 || nparts > order)
+    return fail(SYSTEC_EINVAL, "systec_mttkrp_partial: bad partition");
+  int sum = 0;
+  for (int q = 0; q < nparts; ++q) {
+    if (part_sizes[q] < 1) return fail(SYSTEC_EINVAL, "systec_mttkrp_partial: empty part");
+    sum += part_sizes[q];
+  }
+  if (sum != order) return fail(SYSTEC_EINVAL, "systec_mttkrp_partial: parts must sum to order");
+  if (!F) return fail(SYSTEC_EINVAL, "systec_mttkrp_partial: NULL factor array");
+  for (int q = 0; q < nparts; ++q)
+    if (!F[q]) return fail(SYSTEC_EINVAL, "systec_mttkrp_partial: NULL factor");
+  if ((rc = check_factor_args("systec_mttkrp_partial", I, F[0], fdt, R, C))) return rc;
+  return launch_mttkrp_partial(order, nparts, part_sizes, I, nnz, idx, val, F, fdt, R, C,
+                               static_cast<hipStream_t>(stream));
+}
+
+int systec_cp_step(const systec_tensor* t, const void* B, systec_dtype bdt, int64_t R, float* C,
+                   float* B_new, float* G, double* fit, systec_stream stream) {
+  if (!t || !t->impl) return fail(SYSTEC_EINVAL, "systec_cp_step: NULL handle");
+  const Tensor* tn = t->impl;
+  if (tn->kind != 1) return fail(SYSTEC_EINVAL, "systec_cp_step: not an order-3..5 tensor");
+  int rc = check_factor_args("systec_cp_step", tn->dim, B, bdt, R, C);
+  if (rc) return rc;
+  if (R > 64) return fail(SYSTEC_EINVAL, "systec_cp_step: R must be at most 64");
+  if (!B_new || !G || !fit) return fail(SYSTEC_EINVAL, "systec_cp_step: NULL pointer");
+  return launch_cp_step(tn, B, bdt, R, C, B_new, G, fit, static_cast<hipStream_t>(stream));
+}
+
 int systec_ssymv_t(const systec_tensor* t, const void* x, systec_dtype xdt, float* y,
                    systec_stream stream) {
   if (!t || !t->impl) return fail(SYSTEC_EINVAL, "systec_ssymv_t: NULL handle");

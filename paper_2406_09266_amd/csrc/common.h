@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -112,12 +113,27 @@ struct Tensor {
   int32_t* chunk_panel = nullptr;
   int32_t* chunk_tile_begin = nullptr;
   int32_t* chunk_tile_end = nullptr;
+  // entry index where the chunk's padding starts (padding entries hold
+  // value 0, which is no contribution to a sum but is one to a minimum)
+  int32_t* chunk_valid_end = nullptr;
   std::vector<int32_t> h_chunk_panel, h_chunk_tile_begin, h_chunk_tile_end;  // host copies
   // vertex relabeling (matrix prepared with its vertices ordered by degree):
   // the panels hold P A P^T; perm[new] = old, inv[old] = new
   bool relabeled = false;
   int32_t* perm = nullptr;
   int32_t* inv = nullptr;
+  // work buffers of a prepared matrix, allocated with it so that a call
+  // allocates nothing: the input and output in the stored vertex order (a
+  // relabeled matrix: n elements each) and SYPRD's per-chunk partials. Calls
+  // that use them hold work_mu while they enqueue and wait on the device for
+  // the previous user (work_done), so calls on different streams that share
+  // the handle run one after another on the device.
+  void* work_x = nullptr;
+  float* work_y = nullptr;
+  float* work_partial = nullptr;
+  mutable std::mutex work_mu;
+  mutable hipEvent_t work_done = nullptr;
+  mutable bool work_recorded = false;
   // tensor
   int64_t vnnz[5] = {0, 0, 0, 0, 0};
   // Fewer than kShortRun stored entries per index on average: the views' runs
@@ -133,6 +149,27 @@ struct Tensor {
   ServeUnit* d_units = nullptr;
   std::vector<void*> allocations;
 };
+// Holds a prepared matrix's work buffers for one call: the host lock while
+// the call enqueues, and on the device the call's stream waits for the
+// previous holder's work (any stream) and marks the end of its own.
+class WorkLease {
+ public:
+  WorkLease(const Tensor* t, hipStream_t s) : t_(t), s_(s), lock_(t->work_mu) {
+    if (t_->work_recorded) rc_ = check_hip(hipStreamWaitEvent(s_, t_->work_done, 0),
+                                           "hipStreamWaitEvent");
+  }
+  ~WorkLease() {
+    if (hipEventRecord(t_->work_done, s_) == hipSuccess) t_->work_recorded = true;
+  }
+  int status() const { return rc_; }
+
+ private:
+  const Tensor* t_;
+  hipStream_t s_;
+  std::lock_guard<std::mutex> lock_;
+  int rc_ = SYSTEC_OK;
+};
+
 // relabel: 1 orders the vertices by degree, 0 keeps them, -1 decides from the
 // degree skew.
 int tensor_create_csr(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col,
@@ -159,6 +196,29 @@ int launch_ssymv_panel(const Tensor* t, const void* x, systec_dtype xdt, float* 
                        hipStream_t s);
 int launch_mttkrp_views(const Tensor* t, const void* B, systec_dtype bdt, int64_t R, float* C,
                         hipStream_t s);
+// Bellman-Ford update y[i] = min_j (A[i,j] + d[j]) over the stored
+// coordinates of the symmetric matrix (bellman.hip): over the canonical CSR,
+// and over a prepared matrix (panel format).
+int launch_bellman_ford(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col,
+                        const float* val, const float* d, float* y, hipStream_t s);
+int launch_bellman_ford_panel(const Tensor* t, const float* d, float* y, hipStream_t s);
+// TTM with visible output symmetry (ttm.hip): C[j,l,r] = sum_k T[k,j,l]
+// B[k,r] over canonical 3-index COO; the canonical half j <= l is computed,
+// then copied to the other half if mirror.
+int launch_ttm(int64_t I, int64_t nnz, const int32_t* const* idx, const float* val,
+               const void* B, systec_dtype bdt, int64_t R, float* C, bool mirror,
+               hipStream_t s);
+// MTTKRP of a tensor symmetric within consecutive parts of its slots
+// (mttkrp_partial.hip), one factor matrix per part, output mode 1.
+int launch_mttkrp_partial(int order, int nparts, const int32_t* part_sizes, int64_t I,
+                          int64_t nnz, const int32_t* const* idx, const float* val,
+                          const void* const* F, systec_dtype fdt, int64_t R, float* C,
+                          hipStream_t s);
+// One symmetric CP-ALS step around the prepared tensor's MTTKRP (cp.hip):
+// C = MTTKRP(T, B), G = B^T B, B_new = C (G^(N-1))^-1, fit = {||T||^2,
+// <T,[[B]]>, ||[[B]]||^2, ||T - [[B]]||^2}. R <= 64.
+int launch_cp_step(const Tensor* t, const void* B, systec_dtype bdt, int64_t R, float* C,
+                   float* B_new, float* G, double* fit, hipStream_t s);
 int launch_mttkrp_views_lds(const Tensor* t, const void* B, systec_dtype bdt, int64_t R, float* C,
                             hipStream_t s);
 
@@ -198,15 +258,14 @@ struct ZeroArgs {
   float* ptr[kStepReqs];
   int64_t count[kStepReqs];
 };
-// Prepared SSYMV panels: 16,384 rows (128 KiB of FP64 row sums in LDS; LDS
-// FP64 atomic adds run about 7x faster than FP32 ones on gfx950), run by
-// 1,024-thread workgroups (one per CU).
+// Prepared SSYMV panels: 16,384 rows (64 KiB of FP32 row sums in LDS), run
+// by 1,024-thread workgroups.
 constexpr int kPanelRows = 16384;
 constexpr int kPanelThreads = 1024;
 constexpr int kServeBlock = kPanelThreads;  // SSYMV step kernel
 constexpr int kServeMttkrpBlock = 256; // MTTKRP step kernel
-constexpr int kServeLds = kPanelRows * 8;  // bytes: the FP64 row sums of one panel
-constexpr int kServeLdsStaged = kPanelRows * (8 + 2);  // and the panel's BF16 x slice
+constexpr int kServeLds = kPanelRows * 4;  // bytes: the FP32 row sums of one panel
+constexpr int kServeLdsStaged = kPanelRows * (4 + 2);  // and the panel's BF16 x slice
 // Zeroes the outputs of newly admitted requests; runs on a stream before
 // its step launches.
 int launch_serve_prologue(const ZeroArgs& z, hipStream_t s);

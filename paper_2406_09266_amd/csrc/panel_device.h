@@ -10,9 +10,12 @@ namespace dev {
 
 // SSYMV over one chunk (tiles [tb, te) of panel p) of a matrix in the panel
 // format (see plan.hip), by the whole workgroup, which it synchronizes. The
-// panel's row sums live in LDS as doubles (s_rows, H of them): LDS FP64
-// atomic adds run about 7x faster than FP32 ones on gfx950, and they sum the
-// FP32 products with 53-bit precision. The entries arrive sorted
+// panel's row sums live in LDS as FP32 (s_rows, H of them), added with LDS
+// FP32 atomics (ds_add_f32) and flushed to y once per chunk. On gfx950 these
+// run at about a tenth of the rate of integer and FP64 LDS atomics (measured
+// 0.2 T/s for the device), and every stored entry makes one, so they bound
+// the kernel; a compare-and-swap loop on the LDS word was measured no faster.
+// The entries arrive sorted
 // by column and are taken lane-strided (step k of a wave holds 64 consecutive
 // entries), so the column-side updates y[j] += a x[i] reduce across the wave
 // by a segmented scan per step, and the segment totals leave in one atomic
@@ -30,9 +33,9 @@ __device__ __forceinline__ void ssymv_panel_chunk(int n, int H, int p, int tb, i
                                                   const uint16_t* __restrict__ prow,
                                                   const float* __restrict__ pval,
                                                   const XT* __restrict__ x, float* __restrict__ y,
-                                                  double* s_rows, XT* s_x = nullptr) {
+                                                  float* s_rows, XT* s_x = nullptr) {
   const int r0 = p * H;
-  for (int i = threadIdx.x; i < H; i += blockDim.x) s_rows[i] = 0.0;
+  for (int i = threadIdx.x; i < H; i += blockDim.x) s_rows[i] = 0.0f;
   if constexpr (kStageX) {
     for (int i = threadIdx.x; i < H; i += blockDim.x)
       s_x[i] = r0 + i < n ? x[r0 + i] : XT(0);
@@ -63,13 +66,15 @@ __device__ __forceinline__ void ssymv_panel_chunk(int n, int H, int p, int tb, i
       xc[k] = load_f32(x, c[k]);
       xr[k] = kStageX ? load_f32(s_x, ro[k]) : load_f32(x, r0 + ro[k]);
     }
+    // row side, y[i] += a x[j] (padding entries have a = 0)
+#pragma unroll
+    for (int k = 0; k < kV; ++k)
+      if (a[k] != 0.0f) atomicAdd(s_rows + ro[k], a[k] * xc[k]);
     int carry_key = -1;
     float carry = 0.0f;
 #pragma unroll
     for (int k = 0; k < kV; ++k) {
       const int r = r0 + ro[k];
-      if (a[k] != 0.0f)  // y[i] += a x[j]
-        atomicAdd(s_rows + ro[k], static_cast<double>(a[k] * xc[k]));
       const float v = (c[k] != r) ? a[k] * xr[k] : 0.0f;  // y[j] += a x[i]
       // the previous step's last segment either continues in lane 0 here or
       // is complete and must be written now
@@ -80,7 +85,7 @@ __device__ __forceinline__ void ssymv_panel_chunk(int n, int H, int p, int tb, i
       }
       float seg = wave_seg_sum(c[k], v);
       if (c[k] == carry_key) seg += carry;  // only lanes of the first segment match
-      const int next_key = __shfl_down(c[k], 1);
+      const int next_key = next_lane_i32(c[k], -1);
       const bool ends = lane != kWave - 1 && next_key != c[k];
       if (ends && seg != 0.0f) atomic_add_noret(y + c[k], seg);
       carry_key = __builtin_amdgcn_readlane(c[k], kWave - 1);
@@ -90,7 +95,7 @@ __device__ __forceinline__ void ssymv_panel_chunk(int n, int H, int p, int tb, i
   }
   __syncthreads();
   for (int i = threadIdx.x; i < H; i += blockDim.x) {
-    const float v = static_cast<float>(s_rows[i]);
+    const float v = s_rows[i];
     if (v != 0.0f && r0 + i < n) atomic_add_noret(y + r0 + i, v);
   }
 }

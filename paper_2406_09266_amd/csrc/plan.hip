@@ -266,6 +266,7 @@ int bits_for(int64_t v) {
 
 void tensor_free(Tensor* t) {
   if (!t) return;
+  if (t->work_done) (void)hipEventDestroy(t->work_done);
   for (void* p : t->allocations) (void)hipFree(p);
   delete t;
 }
@@ -390,7 +391,7 @@ int tensor_create_csr(int64_t n, int64_t nnz, const int32_t* rowptr, const int32
   }
   // padded panel offsets and the chunk table (host, P is small)
   std::vector<int32_t> h_start(P + 1, 0), h_pstart(P + 1, 0);
-  std::vector<int32_t> ch_panel, ch_begin, ch_end;
+  std::vector<int32_t> ch_panel, ch_begin, ch_end, ch_valid;
   int64_t pos = 0, ppos = 0;
   for (int p = 0; p < P; ++p) {
     h_start[p] = static_cast<int32_t>(pos);
@@ -401,6 +402,9 @@ int tensor_create_csr(int64_t n, int64_t nnz, const int32_t* rowptr, const int32
       ch_panel.push_back(p);
       ch_begin.push_back(static_cast<int32_t>(tile0 + c));
       ch_end.push_back(static_cast<int32_t>(tile0 + std::min<int64_t>(tiles, c + kChunkTiles)));
+      ch_valid.push_back(static_cast<int32_t>(
+          std::min<int64_t>((tile0 + std::min<int64_t>(tiles, c + kChunkTiles)) * kPanelTile,
+                            ppos + h_counts[p])));
     }
     pos += h_counts[p];
     ppos += tiles * kPanelTile;
@@ -422,6 +426,7 @@ int tensor_create_csr(int64_t n, int64_t nnz, const int32_t* rowptr, const int32
   if (!rc) rc = tensor_alloc(t, &t->chunk_panel, t->nchunks);
   if (!rc) rc = tensor_alloc(t, &t->chunk_tile_begin, t->nchunks);
   if (!rc) rc = tensor_alloc(t, &t->chunk_tile_end, t->nchunks);
+  if (!rc) rc = tensor_alloc(t, &t->chunk_valid_end, t->nchunks);
   const size_t pb = (P + 1) * sizeof(int32_t);
   if (!rc) rc = check_hip(hipMemcpyAsync(d_start, h_start.data(), pb, hipMemcpyHostToDevice, s), "memcpy");
   if (!rc) rc = check_hip(hipMemcpyAsync(d_pstart, h_pstart.data(), pb, hipMemcpyHostToDevice, s), "memcpy");
@@ -430,6 +435,7 @@ int tensor_create_csr(int64_t n, int64_t nnz, const int32_t* rowptr, const int32
     rc = check_hip(hipMemcpyAsync(t->chunk_panel, ch_panel.data(), cb, hipMemcpyHostToDevice, s), "memcpy");
     if (!rc) rc = check_hip(hipMemcpyAsync(t->chunk_tile_begin, ch_begin.data(), cb, hipMemcpyHostToDevice, s), "memcpy");
     if (!rc) rc = check_hip(hipMemcpyAsync(t->chunk_tile_end, ch_end.data(), cb, hipMemcpyHostToDevice, s), "memcpy");
+    if (!rc) rc = check_hip(hipMemcpyAsync(t->chunk_valid_end, ch_valid.data(), cb, hipMemcpyHostToDevice, s), "memcpy");
   }
   if (!rc && nnz > 0) {
     panel_scatter_kernel<<<grid_for(nnz, 256), 256, 0, s>>>(nz, hbits, kout, vout, val, d_start,
@@ -441,6 +447,16 @@ int tensor_create_csr(int64_t n, int64_t nnz, const int32_t* rowptr, const int32
                                                       t->pval);
     rc = check_launch("panel pad kernel");
   }
+  // the calls' work buffers (see Tensor)
+  if (!rc) rc = tensor_alloc(t, &t->work_partial, std::max(1, t->nchunks));
+  if (!rc && t->relabeled) {
+    float* wx = nullptr;
+    rc = tensor_alloc(t, &wx, n);  // x in the stored order, FP32 or BF16
+    t->work_x = wx;
+    if (!rc) rc = tensor_alloc(t, &t->work_y, n);
+  }
+  if (!rc)
+    rc = check_hip(hipEventCreateWithFlags(&t->work_done, hipEventDisableTiming), "hipEventCreate");
   if (!rc) rc = check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
   if (rc) {
     tensor_free(t);

@@ -188,6 +188,12 @@ class GpuExecutor {
         for (size_t k = 0; k < plan.zero.size() && !rc; ++k) {
           const serve::Request* r = plan.zero[k];
           if (kind_of(static_cast<const Tensor*>(r->tensor->payload)) != g) continue;
+          if (r->ready) {  // the caller's work on the request's buffers comes first
+            rc = check_hip(hipStreamWaitEvent(st, static_cast<hipEvent_t>(r->ready.get()), 0),
+                           "hipStreamWaitEvent(request ready)");
+            r->ready.reset();
+            if (rc) break;
+          }
           if (permuted(*r->tensor)) {
             rc = begin_permuted(*r, st);
             ++launched;
@@ -423,6 +429,34 @@ int systec_serve_submit(systec_server* s, int64_t tensor_id, const void* in, sys
   std::string err;
   const int rc = s->sched->submit(tensor_id, in, dt, R, out, arrival_ns, req_id, &err);
   return rc ? serve_fail(rc, err) : SYSTEC_OK;
+}
+
+int systec_serve_submit_after(systec_server* s, int64_t tensor_id, const void* in,
+                              systec_dtype dt, int64_t R, float* out, int64_t arrival_ns,
+                              systec_stream after, int64_t* req_id) {
+  if (!s || !in || !out || !req_id)
+    return serve_fail(SYSTEC_EINVAL, "systec_serve_submit_after: NULL argument");
+  if (dt != SYSTEC_F32 && dt != SYSTEC_BF16)
+    return serve_fail(SYSTEC_EINVAL, "systec_serve_submit_after: unsupported dtype");
+  if (R < 1 || R > 64)
+    return serve_fail(SYSTEC_EINVAL, "systec_serve_submit_after: R must be in 1..64");
+  // a marker after the work enqueued on `after` so far; the server's stream
+  // waits for it before the request's first kernel
+  hipEvent_t ev = nullptr;
+  int rc = check_hip(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "hipEventCreate");
+  if (rc) return rc;
+  std::shared_ptr<void> ready(ev, [](void* e) { (void)hipEventDestroy(static_cast<hipEvent_t>(e)); });
+  rc = check_hip(hipEventRecord(ev, static_cast<hipStream_t>(after)), "hipEventRecord");
+  if (rc) return rc;
+  std::string err;
+  rc = s->sched->submit(tensor_id, in, dt, R, out, arrival_ns, req_id, &err, std::move(ready));
+  return rc ? serve_fail(rc, err) : SYSTEC_OK;
+}
+
+int systec_tensor_bytes(const systec_tensor* t, uint64_t* bytes) {
+  if (!t || !t->impl || !bytes) return fail(SYSTEC_EINVAL, "systec_tensor_bytes: NULL argument");
+  *bytes = t->impl->bytes;
+  return SYSTEC_OK;
 }
 
 int systec_serve_poll(systec_server* s, int64_t req_id, int* state) {

@@ -106,6 +106,10 @@ struct Request {
   int64_t last_step = -1;
   int part = 0;  // the executor part (stream) that runs this request's work
   std::string error;
+  // Executor-owned marker of the caller's work that must finish before the
+  // request's own work starts (its input written, its output free); the
+  // executor takes it when it first schedules the request's work.
+  mutable std::shared_ptr<void> ready;
 };
 
 // Units [unit0, unit0 + count) of a request's operand, run in one step.
@@ -180,7 +184,8 @@ class Scheduler {
   }
 
   int submit(int64_t tensor_id, const void* in, int dtype, int64_t R, float* out,
-             int64_t arrival_ns, int64_t* req_id, std::string* err) {
+             int64_t arrival_ns, int64_t* req_id, std::string* err,
+             std::shared_ptr<void> ready = nullptr) {
     std::unique_lock<std::mutex> lk(mu_);
     auto it = tensors_.find(tensor_id);
     if (it == tensors_.end()) {
@@ -210,6 +215,7 @@ class Scheduler {
     r->R = R;
     r->bytes = b;
     r->arrival_ns = arrival_ns > 0 ? arrival_ns : now_ns();
+    r->ready = std::move(ready);
     requests_[r->id] = r;
     queue_.push_back(r);
     ++submitted_;

@@ -93,15 +93,14 @@ __device__ __forceinline__ void view_range(const ServeTensor* t, const ServeUnit
                                     0, q.R);
 }
 
-// SSYMV items need the panel's row sums in LDS (1,024 threads, 128 KiB, and
-// 32 KiB more for a BF16 request's staged x slice where the device allows
-// 160 KiB per workgroup); MTTKRP
+// SSYMV items need the panel's row sums in LDS (1,024 threads, 64 KiB, and
+// 32 KiB more for a BF16 request's staged x slice); MTTKRP
 // items need no LDS and run at full occupancy (256 threads, one kernel per
 // tensor order so that each keeps the registers of its own order); the four
 // waves of an MTTKRP workgroup share an item of a few tiles each.
 template <bool kStageX>
 __global__ __launch_bounds__(kServeBlock) void serve_ssymv_kernel(StepArgs a) {
-  extern __shared__ double s_lds[];
+  extern __shared__ float s_lds[];
   const int i = blockIdx.x;
   const StepReq& r = a.req[find_req(a, i)];
   const ServeTensor* t = r.t;

@@ -21,6 +21,7 @@
 // sequentially by row; the wave combines the segments that cross lanes with a
 // DPP segmented scan, so a row spanning a whole tile costs one atomic.
 #include "common.h"
+#include "csr_tile.h"
 #include "panel_device.h"
 #include "wave_ops.h"
 
@@ -31,112 +32,6 @@ using namespace dev;
 
 constexpr int kWaves = 4;             // wavefronts per workgroup
 constexpr int kBlock = kWave * kWaves;
-
-// Merge-path split (Merrill & Garland's merge-based CSR decomposition): the
-// rows' end offsets and the entry indices form one sorted sequence of n + nnz
-// items; diagonal d of it splits at the largest row i in [0, n] with
-// rowptr[i] + i <= d. The wave searches cooperatively, 64 probes per step.
-__device__ __forceinline__ int merge_split(const int32_t* __restrict__ rowptr, int n,
-                                           int64_t d, int lane) {
-  int lo = 0, hi = n + 1;  // f(lo) <= d; hi == n+1 or f(hi) > d
-  while (hi - lo > 1) {
-    const int step = (hi - lo + kWave - 1) / kWave;
-    const int probe = lo + (lane + 1) * step;
-    const bool le = probe < hi && static_cast<int64_t>(rowptr[probe]) + probe <= d;
-    const int c = __popcll(__ballot(le));
-    const int nlo = lo + c * step;
-    hi = min(hi, lo + (c + 1) * step);
-    lo = nlo;
-  }
-  return lo;
-}
-
-// The entries of one merge-path tile, lane-contiguous: lane l holds tile
-// entries 8l .. 8l+7 (entries past the tile's end get val = 0 and the last
-// row).
-struct LaneEntries {
-  int row[kV];
-  int col[kV];
-  float val[kV];
-  int valid;  // number of valid entries of this lane (0..8)
-};
-
-// Per-wave LDS staging: row-start markers and the tile's columns and values.
-struct TileLds {
-  int head[kTile];
-  int col[kTile];
-  float val[kTile];
-};
-
-// Loads merge-path tile `tile` (items [tile*kTile, (tile+1)*kTile) of the
-// n + nnz sequence): at most kTile rows and kTile entries. Returns false if
-// the tile holds no entry.
-__device__ __forceinline__ bool load_tile(const int32_t* __restrict__ rowptr,
-                                          const int32_t* __restrict__ col,
-                                          const float* __restrict__ val, int n, int nnz,
-                                          int64_t tile, int lane, TileLds& S, LaneEntries& L) {
-  const int64_t total = static_cast<int64_t>(n) + nnz;
-  const int64_t d0 = tile * kTile;
-  const int64_t d1 = min(d0 + kTile, total);
-  const int i0 = merge_split(rowptr, n, d0, lane);
-  const int i1 = merge_split(rowptr, n, d1, lane);
-  const int j0 = static_cast<int>(d0 - i0);
-  const int j1 = static_cast<int>(d1 - i1);
-  const int cnt = j1 - j0;  // 0..kTile
-  if (cnt <= 0) return false;
-
-  // row-start markers: head[p] = largest row whose first entry is j0 + p
-  {
-    int4* h4 = reinterpret_cast<int4*>(S.head + lane * kV);
-    const int4 none = make_int4(-1, -1, -1, -1);
-    h4[0] = none;
-    h4[1] = none;
-  }
-  wave_sync();
-  if (lane == 0) S.head[0] = i0;
-  wave_sync();
-  // rows (i0, i1] start at or after j0; at most kTile of them
-  for (int r = i0 + 1 + lane; r <= i1; r += kWave) {
-    const int s = rowptr[r];
-    if (s < j1) atomicMax(S.head + (s - j0), r);
-  }
-  // coalesced loads of the tile's entries into LDS
-#pragma unroll
-  for (int q = 0; q < kV; ++q) {
-    const int p = q * kWave + lane;
-    if (p < cnt) {
-      S.col[p] = col[j0 + p];
-      S.val[p] = val[j0 + p];
-    }
-  }
-  wave_sync();
-
-  int h[kV];
-  read8(S.head + lane * kV, h);
-#pragma unroll
-  for (int k = 1; k < kV; ++k) h[k] = max(h[k], h[k - 1]);
-  // carry-in: the largest marker of all earlier lanes
-  const int incl = wave_incl_max(h[kV - 1]);
-  int carry = __shfl_up(incl, 1);
-  if (lane == 0) carry = INT_MIN;
-#pragma unroll
-  for (int k = 0; k < kV; ++k) L.row[k] = max(h[k], carry);
-
-  L.valid = max(0, min(kV, cnt - lane * kV));
-  int c[kV];
-  read8(S.col + lane * kV, c);
-  const float* vp = S.val + lane * kV;
-  const float4 va = reinterpret_cast<const float4*>(vp)[0];
-  const float4 vb = reinterpret_cast<const float4*>(vp)[1];
-  const float v[kV] = {va.x, va.y, va.z, va.w, vb.x, vb.y, vb.z, vb.w};
-#pragma unroll
-  for (int k = 0; k < kV; ++k) {
-    const bool ok = k < L.valid;
-    L.col[k] = ok ? c[k] : L.row[k];
-    L.val[k] = ok ? v[k] : 0.0f;
-  }
-  return true;
-}
 
 // y (+)= A x over one tile. kSym: the stored entries are the upper triangle
 // and each off-diagonal entry also updates y[col].
@@ -234,7 +129,7 @@ __global__ __launch_bounds__(1024) void reduce_partials_f64(const float* __restr
   }
 }
 
-// kStageX: the panel's slice of x follows the row sums in LDS (H doubles,
+// kStageX: the panel's slice of x follows the row sums in LDS (H floats,
 // then H elements of x).
 template <typename XT, bool kStageX>
 __global__ __launch_bounds__(kPanelThreads) void ssymv_panel_kernel(
@@ -242,7 +137,7 @@ __global__ __launch_bounds__(kPanelThreads) void ssymv_panel_kernel(
     const int32_t* __restrict__ chunk_tile_begin, const int32_t* __restrict__ chunk_tile_end,
     const int32_t* __restrict__ pcol, const uint16_t* __restrict__ prow,
     const float* __restrict__ pval, const XT* __restrict__ x, float* __restrict__ y) {
-  extern __shared__ double s_rows[];  // the panel's row sums
+  extern __shared__ float s_rows[];  // the panel's row sums
   const int chunk = blockIdx.x;
   ssymv_panel_chunk<XT, kStageX>(n, H, chunk_panel[chunk], chunk_tile_begin[chunk],
                                  chunk_tile_end[chunk], pcol, prow, pval, x, y, s_rows,
@@ -397,7 +292,7 @@ namespace {
 template <typename XT, bool kStageX>
 int panel_launch(const Tensor* t, const XT* x, float* y, hipStream_t s) {
   const size_t H = static_cast<size_t>(t->panel_rows);
-  const size_t lds = H * sizeof(double) + (kStageX ? H * sizeof(XT) : 0);
+  const size_t lds = H * sizeof(float) + (kStageX ? H * sizeof(XT) : 0);
   const void* kern = reinterpret_cast<const void*>(ssymv_panel_kernel<XT, kStageX>);
   // more than the default 64 KiB of dynamic LDS
   const int rc = check_hip(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -418,7 +313,7 @@ int panel_call(const Tensor* t, const void* x, systec_dtype xdt, float* y, bool 
   if (rc != SYSTEC_OK || t->nchunks == 0) return rc;
   if (xdt == SYSTEC_F32) return panel_launch<float, false>(t, static_cast<const float*>(x), y, s);
   // BF16 x: the panel's slice of x goes to LDS beside the row sums when the
-  // device allows that much per workgroup (16384 rows: 160 KiB)
+  // device allows that much per workgroup (16384 rows: 96 KiB)
   int dev = 0;
   int limit = 0;
   rc = check_hip(hipGetDevice(&dev), "hipGetDevice");
@@ -426,7 +321,7 @@ int panel_call(const Tensor* t, const void* x, systec_dtype xdt, float* y, bool 
     rc = check_hip(hipDeviceGetAttribute(&limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev),
                    "hipDeviceGetAttribute(max shared memory)");
   if (rc) return rc;
-  const size_t staged = static_cast<size_t>(t->panel_rows) * (sizeof(double) + sizeof(uint16_t));
+  const size_t staged = static_cast<size_t>(t->panel_rows) * (sizeof(float) + sizeof(uint16_t));
   const uint16_t* xb = static_cast<const uint16_t*>(x);
   return staged <= static_cast<size_t>(limit) ? panel_launch<uint16_t, true>(t, xb, y, s)
                                               : panel_launch<uint16_t, false>(t, xb, y, s);
@@ -457,14 +352,12 @@ int launch_permute_out(int n, const int32_t* inv, const float* yp, float* y, hip
 namespace {
 
 // The prepared SYPRD over a matrix in its own vertex order (x already in
-// that order).
+// that order); the caller holds the work lease (per-chunk partials).
 int syprd_panel_call(const Tensor* t, const void* x, systec_dtype xdt, double* out,
                      hipStream_t s) {
   const int nch = std::max(1, t->nchunks);
-  float* partial = nullptr;
-  int rc = check_hip(hipMallocAsync(reinterpret_cast<void**>(&partial), nch * sizeof(float), s),
-                     "hipMallocAsync(syprd partials)");
-  if (rc) return rc;
+  float* partial = t->work_partial;
+  int rc = SYSTEC_OK;
   if (t->nchunks == 0) {
     fill_f32_kernel<<<1, 64, 0, s>>>(partial, 1);
     rc = check_launch("syprd partial clear");
@@ -494,26 +387,19 @@ int syprd_panel_call(const Tensor* t, const void* x, systec_dtype xdt, double* o
     reduce_partials_f64<<<dim3(1), dim3(1024), 0, s>>>(partial, nch, out);
     rc = check_launch("syprd final reduction");
   }
-  const int rc2 = check_hip(hipFreeAsync(partial, s), "hipFreeAsync(syprd partials)");
-  return rc ? rc : rc2;
+  return rc;
 }
 
 }  // namespace
 
 int launch_syprd_panel(const Tensor* t, const void* x, systec_dtype xdt, double* out,
                        hipStream_t s) {
-  if (!t->relabeled) return syprd_panel_call(t, x, xdt, out, s);
+  WorkLease lease(t, s);
+  if (lease.status()) return lease.status();
+  if (!t->relabeled || t->dim == 0) return syprd_panel_call(t, x, xdt, out, s);
   // relabeled matrix: s = x_p^T (P A P^T) x_p with x_p[i] = x[perm[i]]
-  const int n = static_cast<int>(t->dim);
-  if (n == 0) return syprd_panel_call(t, x, xdt, out, s);
-  void* xp = nullptr;
-  int rc = check_hip(hipMallocAsync(&xp, static_cast<size_t>(n) * (xdt == SYSTEC_F32 ? 4 : 2), s),
-                     "hipMallocAsync(permuted x)");
-  if (rc) return rc;
-  rc = launch_permute_in(n, t->perm, x, xdt, xp, nullptr, s);
-  if (!rc) rc = syprd_panel_call(t, xp, xdt, out, s);
-  const int rc2 = check_hip(hipFreeAsync(xp, s), "hipFreeAsync");
-  return rc ? rc : rc2;
+  const int rc = launch_permute_in(static_cast<int>(t->dim), t->perm, x, xdt, t->work_x, nullptr, s);
+  return rc ? rc : syprd_panel_call(t, t->work_x, xdt, out, s);
 }
 
 int launch_ssymv_panel_stored(const Tensor* t, const void* x, systec_dtype xdt, float* y,
@@ -523,33 +409,24 @@ int launch_ssymv_panel_stored(const Tensor* t, const void* x, systec_dtype xdt, 
 
 int launch_syprd_panel_stored(const Tensor* t, const void* x, systec_dtype xdt, double* out,
                               hipStream_t s) {
+  WorkLease lease(t, s);
+  if (lease.status()) return lease.status();
   return syprd_panel_call(t, x, xdt, out, s);
 }
 
 int launch_ssymv_panel(const Tensor* t, const void* x, systec_dtype xdt, float* y,
                        hipStream_t s) {
   if (!t->relabeled) return panel_call(t, x, xdt, y, false, s);
-  // relabeled matrix: x in the prepared order, the panels, y back in the
-  // caller's order (stream-ordered scratch)
+  // relabeled matrix: x into the stored order (clearing the stored-order
+  // output), the panels, y back into the caller's order
   const int n = static_cast<int>(t->dim);
   if (n == 0) return SYSTEC_OK;
-  const size_t xb = static_cast<size_t>(n) * (xdt == SYSTEC_F32 ? 4 : 2);
-  void* xp = nullptr;
-  float* yp = nullptr;
-  int rc = check_hip(hipMallocAsync(&xp, xb, s), "hipMallocAsync(permuted x)");
-  if (rc) return rc;
-  rc = check_hip(hipMallocAsync(reinterpret_cast<void**>(&yp), static_cast<size_t>(n) * sizeof(float), s),
-                 "hipMallocAsync(permuted y)");
-  if (rc) {
-    (void)hipFreeAsync(xp, s);
-    return rc;
-  }
-  rc = launch_permute_in(n, t->perm, x, xdt, xp, yp, s);
-  if (!rc) rc = panel_call(t, xp, xdt, yp, true, s);
-  if (!rc) rc = launch_permute_out(n, t->inv, yp, y, s);
-  const int rc2 = check_hip(hipFreeAsync(xp, s), "hipFreeAsync");
-  const int rc3 = check_hip(hipFreeAsync(yp, s), "hipFreeAsync");
-  return rc ? rc : (rc2 ? rc2 : rc3);
+  WorkLease lease(t, s);
+  int rc = lease.status();
+  if (!rc) rc = launch_permute_in(n, t->perm, x, xdt, t->work_x, t->work_y, s);
+  if (!rc) rc = panel_call(t, t->work_x, xdt, t->work_y, true, s);
+  if (!rc) rc = launch_permute_out(n, t->inv, t->work_y, y, s);
+  return rc;
 }
 
 }  // namespace systec

@@ -22,6 +22,13 @@ __device__ __forceinline__ float dpp_f32(float old, float src) {
                                   false));
 }
 
+// The value of the next lane (lane 63 gets `last`), by the DPP whole-wave
+// shift (wave_shl:1), which, unlike a shuffle through ds_bpermute, does not
+// wait for the LDS operations still in flight.
+__device__ __forceinline__ int next_lane_i32(int v, int last) {
+  return dpp_i32<0x130, 0xf>(last, v);
+}
+
 // Inclusive max-scan over the 64 lanes.
 __device__ __forceinline__ int wave_incl_max(int v) {
   v = max(v, dpp_i32<0x111, 0xf>(INT_MIN, v));
@@ -49,6 +56,25 @@ __device__ __forceinline__ float wave_seg_sum(int key, float v) {
   SYSTEC_SEG_STEP(0x142, 0xa)
   SYSTEC_SEG_STEP(0x143, 0xc)
 #undef SYSTEC_SEG_STEP
+  return v;
+}
+
+// Inclusive segmented minimum over the 64 lanes (segments as for
+// wave_seg_sum; +inf is the identity).
+__device__ __forceinline__ float wave_seg_min(int key, float v) {
+#define SYSTEC_SEGMIN_STEP(CTRL, MASK)                      \
+  {                                                         \
+    const int k2 = dpp_i32<CTRL, MASK>(-2, key);            \
+    const float v2 = dpp_f32<CTRL, MASK>(INFINITY, v);      \
+    v = (k2 == key) ? fminf(v, v2) : v;                     \
+  }
+  SYSTEC_SEGMIN_STEP(0x111, 0xf)
+  SYSTEC_SEGMIN_STEP(0x112, 0xf)
+  SYSTEC_SEGMIN_STEP(0x114, 0xf)
+  SYSTEC_SEGMIN_STEP(0x118, 0xf)
+  SYSTEC_SEGMIN_STEP(0x142, 0xa)
+  SYSTEC_SEGMIN_STEP(0x143, 0xc)
+#undef SYSTEC_SEGMIN_STEP
   return v;
 }
 

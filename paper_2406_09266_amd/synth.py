@@ -240,6 +240,37 @@ def sym_coo(order, dim, nnz, repeat_frac, seed, R=None, class_cap=0.5):
     return out
 
 
+def partial_coo(parts, dim, nnz, repeat_frac, seed, R=None):
+    """Random tensor symmetric inside consecutive parts of its slots (part
+    sizes `parts`), in canonical COO: indices ascending inside every part,
+    tuples unique, the list sorted lexicographically. Uniform iid indices;
+    in a fraction repeat_frac of the tuples one random adjacent pair of
+    slots inside a part of size >= 2 is made equal (so repeated indices
+    occur at every position). Values N(0,1) FP64; with R, one factor
+    U(-1,1) (dim x R) per part. At most nnz tuples (duplicates dropped)."""
+    rng = _rng(seed)
+    order = int(sum(parts))
+    t = rng.integers(0, dim, (nnz, order))
+    starts = np.cumsum([0] + list(parts[:-1]))
+    multi = [(int(s0), int(q)) for s0, q in zip(starts, parts) if q >= 2]
+    rep = np.flatnonzero(rng.random(nnz) < repeat_frac) if multi else np.empty(0, np.int64)
+    for e in rep:
+        start, size = multi[int(rng.integers(0, len(multi)))]
+        k = start + int(rng.integers(0, size - 1))
+        t[e, k + 1] = t[e, k]
+    s0 = 0
+    for q in parts:
+        t[:, s0:s0 + q] = np.sort(t[:, s0:s0 + q], axis=1)
+        s0 += q
+    t = np.unique(t, axis=0)  # sorted lexicographically, unique
+    idx = np.ascontiguousarray(t.T.astype(np.int32))
+    out = {"parts": list(parts), "order": order, "dim": dim, "idx": idx,
+           "val": rng.standard_normal(idx.shape[1])}
+    if R is not None:
+        out["F"] = [rng.uniform(-1.0, 1.0, (dim, R)) for _ in parts]
+    return out
+
+
 def dense_uniform(shape, seed, low=-1.0, high=1.0):
     return _rng(seed).uniform(low, high, shape)
 

@@ -1,0 +1,134 @@
+"""GPU parity of the kernels built next to SSYMV and MTTKRP: TTM with the
+output's visible symmetry and MTTKRP of a partially symmetric tensor,
+against the FP64 oracle, element by element (|got - want| <= 1e-5 of each
+element's scale, the oracle on absolute values), plus the BF16 end-to-end
+bound of 2e-2."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2406_09266_amd as systec
+from paper_2406_09266_amd import synth
+
+from gpu_util import assert_elementwise, dev, f32, rel_err
+
+pytestmark = pytest.mark.gpu
+TOL32 = 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    yield
+    torch.cuda.synchronize()
+
+
+def _factor(B, bdtype):
+    Bd = dev(B.astype(np.float32))
+    if bdtype == "bf16":
+        return systec.quantize_bf16(Bd), oracle.round_bf16(B.astype(np.float32))
+    return Bd, f32(B)
+
+
+# ---------------------------------------------------------------------- TTM --
+
+@pytest.mark.parametrize("dim,nnz", [(40, 5003), (200, 100007), (1000, 300001)])
+@pytest.mark.parametrize("R", [1, 16, 33])
+@pytest.mark.parametrize("bdtype", ["f32", "bf16"])
+def test_ttm_matches_oracle(dim, nnz, R, bdtype):
+    t = synth.sym_coo(3, dim, nnz, repeat_frac=0.2, seed=900 + dim + R)
+    B = synth.dense_uniform((dim, R), seed=R + 3)
+    print(f"ttm dim={dim} nnz={nnz} R={R} B={bdtype}", flush=True)
+    Bd, Bref = _factor(B, bdtype)
+    C = systec.ttm([dev(a) for a in t["idx"]], dev(t["val"].astype(np.float32)), Bd).cpu().numpy()
+    v32 = f32(t["val"])
+    want, counts = oracle.ttm3(dim, t["idx"].T, v32, Bref)
+    assert all(h > 0 for h in counts["hist"])
+    scale, _ = oracle.ttm3(dim, t["idx"].T, np.abs(v32), np.abs(Bref))
+    assert_elementwise(C, want, scale, TOL32, "ttm")
+    # the copy pass made C exactly symmetric in (j, l)
+    np.testing.assert_array_equal(C, C.transpose(1, 0, 2))
+    if bdtype == "bf16":
+        e2e, _ = oracle.ttm3(dim, t["idx"].T, t["val"], B)
+        assert rel_err(C, e2e) <= 2e-2
+
+
+def test_ttm_canonical_half_only_and_empty():
+    """mirror=False writes the canonical half (j <= l) only; an empty tensor
+    gives zeros there."""
+    import torch
+    dim, R = 60, 8
+    t = synth.sym_coo(3, dim, 4000, repeat_frac=0.2, seed=31)
+    B = synth.dense_uniform((dim, R), seed=32)
+    out = torch.full((dim, dim, R), 7.0, device="cuda")
+    C = systec.ttm([dev(a) for a in t["idx"]], dev(t["val"].astype(np.float32)),
+                   dev(B.astype(np.float32)), out=out, mirror=False).cpu().numpy()
+    want, _ = oracle.ttm3(dim, t["idx"].T, f32(t["val"]), f32(B))
+    scale, _ = oracle.ttm3(dim, t["idx"].T, np.abs(f32(t["val"])), np.abs(f32(B)))
+    up = np.triu(np.ones((dim, dim), bool))
+    assert_elementwise(C[up], want[up], scale[up], TOL32, "ttm canonical half")
+    assert np.all(C[~up] == 7.0)
+    empty = [torch.empty(0, dtype=torch.int32, device="cuda") for _ in range(3)]
+    Ce = systec.ttm(empty, torch.empty(0, device="cuda"), dev(B.astype(np.float32)),
+                    out=torch.full((dim, dim, R), 5.0, device="cuda"))
+    assert torch.count_nonzero(Ce).item() == 0
+
+
+# --------------------------------------------- partially symmetric MTTKRP --
+
+PARTITIONS = [[2, 2], [3, 1], [1, 3], [2, 1, 1], [1, 2, 1], [2, 3], [3, 2], [1, 1, 1],
+              [1, 2, 2], [2, 2, 1], [1, 1, 1, 1, 1], [2, 1]]
+
+
+@pytest.mark.parametrize("parts", PARTITIONS, ids=lambda p: "-".join(map(str, p)))
+@pytest.mark.parametrize("R", [1, 16, 40])
+@pytest.mark.parametrize("bdtype", ["f32", "bf16"])
+def test_partial_mttkrp_matches_oracle(parts, R, bdtype):
+    order = sum(parts)
+    dim = {2: 400, 3: 300, 4: 100, 5: 50}[order]
+    t = synth.partial_coo(parts, dim, 30000, repeat_frac=0.3, seed=1000 + 10 * order + R, R=R)
+    print(f"partial mttkrp parts={parts} nnz={t['val'].size} R={R} F={bdtype}", flush=True)
+    Fd, Fref = zip(*[_factor(f, bdtype) for f in t["F"]])
+    C = systec.mttkrp_partial(parts, [dev(a) for a in t["idx"]], dev(t["val"].astype(np.float32)),
+                              list(Fd)).cpu().numpy()
+    v32 = f32(t["val"])
+    want, _ = oracle.mttkrp_partial(parts, dim, t["idx"].T, v32, list(Fref))
+    scale, _ = oracle.mttkrp_partial(parts, dim, t["idx"].T, np.abs(v32),
+                                     [np.abs(f) for f in Fref])
+    assert_elementwise(C, want, scale, TOL32, f"partial mttkrp {parts}")
+    if bdtype == "bf16":
+        e2e, _ = oracle.mttkrp_partial(parts, dim, t["idx"].T, t["val"], t["F"])
+        assert rel_err(C, e2e) <= 2e-2
+
+
+@pytest.mark.parametrize("order", [3, 4, 5])
+def test_partial_mttkrp_one_part_is_the_symmetric_kernel(order):
+    dim = {3: 300, 4: 120, 5: 60}[order]
+    t = synth.sym_coo(order, dim, 15000, repeat_frac=0.2, seed=40 + order)
+    B = dev(synth.dense_uniform((dim, 16), seed=41).astype(np.float32))
+    idx = [dev(a) for a in t["idx"]]
+    val = dev(t["val"].astype(np.float32))
+    C1 = systec.mttkrp_partial([order], idx, val, [B]).cpu().numpy()
+    C2 = systec.mttkrp(idx, val, B).cpu().numpy()
+    assert rel_err(C1, C2) <= TOL32
+
+
+def test_partial_mttkrp_rejects_bad_partitions():
+    from paper_2406_09266_amd import _lib
+    t = synth.partial_coo([2, 2], 20, 100, 0.0, seed=3, R=4)
+    idx = [dev(a) for a in t["idx"]]
+    val = dev(t["val"].astype(np.float32))
+    F = [dev(f.astype(np.float32)) for f in t["F"]]
+    with pytest.raises(ValueError):
+        systec.mttkrp_partial([2, 1], idx, val, F)  # parts do not sum to the order
+    import ctypes
+    sizes = np.array([2, 3], np.int32)  # sum 5 != order 4, caught by the library too
+    pp, keep = _lib.ptr_array([a.data_ptr() for a in idx])
+    fp, fkeep = _lib.ptr_array([f.data_ptr() for f in F])
+    C = dev(np.zeros((20, 4), np.float32))
+    rc = _lib.lib().systec_mttkrp_partial(4, 2, ctypes.c_void_p(sizes.ctypes.data), 20,
+                                          val.numel(), pp, ctypes.c_void_p(val.data_ptr()), fp,
+                                          0, 4, ctypes.c_void_p(C.data_ptr()), None)
+    assert rc == 1

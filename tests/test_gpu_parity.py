@@ -19,7 +19,7 @@ import oracle
 import paper_2406_09266_amd as systec
 from paper_2406_09266_amd import synth
 
-from gpu_util import dev, f32, rel_err
+from gpu_util import assert_elementwise, dev, f32, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -268,36 +268,52 @@ def test_quantize_matches_oracle_rounding():
     np.testing.assert_array_equal(q, oracle.round_bf16(x))
 
 
-# -------------------------------------------- full-size workloads (sampled) --
+# ------------------------------------------- non-symmetric comparison path --
 
-def _sample_rows(dim, k, seed):
-    rng = np.random.Generator(np.random.PCG64(seed))
-    rows = np.unique(np.concatenate([[0, 1, dim - 1], rng.integers(0, dim, k)]))
-    mask = np.zeros(dim, dtype=np.uint8)
-    mask[rows] = 1
-    return rows, mask
+@pytest.mark.parametrize("order,dim,nnz", [(3, 300, 20011), (4, 120, 15013), (5, 60, 9001)])
+def test_expand_coo_bit_exact(order, dim, nnz):
+    """The expansion behind the non-symmetric MTTKRP: the count, the grouping
+    by the first index, and the multiset of expanded coordinates with their
+    values, bit-exact against the oracle's enumeration."""
+    t = synth.sym_coo(order, dim, nnz, repeat_frac=0.2, seed=500 + order)
+    idx = [dev(a) for a in t["idx"]]
+    val32 = t["val"].astype(np.float32)
+    fidx, fval = systec.expand_coo(idx, dev(val32), dim)
+    r = oracle.expand(order, dim, t["idx"].T, coords_cap=10**7, per_entry=True)
+    got = np.stack([a.cpu().numpy() for a in fidx], axis=1)
+    assert got.shape[0] == r["effective_nnz"]
+    assert np.all(np.diff(got[:, 0]) >= 0)  # grouped by the first index, rows ascending
+    want = r["coords"]
+    # coordinates: the same multiset (sorted lexicographically on both sides)
+    go = np.lexsort(got.T[::-1])
+    wo = np.lexsort(want.T[::-1])
+    np.testing.assert_array_equal(got[go], want[wo])
+    # values: each expanded coordinate carries the value of the stored entry
+    # it expands (the oracle lists an entry's permutations consecutively)
+    wval = np.repeat(val32, r["per_entry"])
+    np.testing.assert_array_equal(fval.cpu().numpy()[go], wval[wo])
 
 
-def test_full_size_ssymv_rmat():
-    m = synth.workload("ssymv_rmat")
-    print(f"ssymv_rmat n={m['n']} nnz={m['col'].size}", flush=True)
-    for xdtype in ("f32", "bf16"):
-        y, want, counts = _ssymv_case(m, xdtype)
-        assert rel_err(y, want) <= TOL32, xdtype
-    rows = np.repeat(np.arange(m["n"], dtype=np.int32), np.diff(m["rowptr"]))
-    hist, eff = systec.expansion_stats([dev(rows), dev(m["col"])], m["n"])
-    assert eff == counts["effective_nnz"] and hist == counts["hist"]
-
-
-@pytest.mark.parametrize("name", ["mttkrp3", "mttkrp5"])
-def test_full_size_mttkrp_sampled_rows(name):
-    t = synth.workload(name)
-    B = t["B"]
-    print(f"{name} I={t['dim']} nnz={t['val'].size} R={B.shape[1]}", flush=True)
-    rows, mask = _sample_rows(t["dim"], 200, seed=5)
-    for bdtype in ("f32", "bf16"):
-        C = _mttkrp(t, B, bdtype)
-        want, counts = _oracle_mttkrp(t, B, bdtype, row_mask=mask)
-        assert rel_err(C[rows], want[rows]) <= TOL32, bdtype
-    hist, eff = systec.expansion_stats([dev(a) for a in t["idx"]], t["dim"])
-    assert eff == counts["effective_nnz"] and hist == counts["hist"]
+@pytest.mark.parametrize("order,dim,nnz", [(3, 300, 20011), (4, 120, 15013), (5, 60, 9001)])
+@pytest.mark.parametrize("R", [1, 16, 17, 32, 100])
+@pytest.mark.parametrize("bdtype", ["f32", "bf16"])
+def test_nonsymmetric_mttkrp_matches_oracle(order, dim, nnz, R, bdtype):
+    """MTTKRP over the expanded tensor (the paper's non-symmetric baseline)
+    gives the oracle's result, element by element."""
+    t = synth.sym_coo(order, dim, nnz, repeat_frac=0.2, seed=600 + order * 7 + R)
+    B = synth.dense_uniform((dim, R), seed=R + 1)
+    print(f"non-symmetric mttkrp order={order} R={R} B={bdtype}", flush=True)
+    idx = [dev(a) for a in t["idx"]]
+    fidx, fval = systec.expand_coo(idx, dev(t["val"].astype(np.float32)), dim)
+    Bd = dev(B.astype(np.float32))
+    if bdtype == "bf16":
+        Bd = systec.quantize_bf16(Bd)
+    C = systec.mttkrp_full(fidx, fval, Bd).cpu().numpy()
+    want, _ = _oracle_mttkrp(t, B, bdtype)
+    Bref = f32(B) if bdtype == "f32" else _bf16_round(B)
+    scale, _ = oracle.mttkrp(order, dim, t["idx"].T, np.abs(f32(t["val"])), np.abs(Bref))
+    assert_elementwise(C, want, scale, TOL32, "non-symmetric mttkrp")
+    assert rel_err(C, want) <= TOL32
+    if bdtype == "bf16":
+        full, _ = oracle.mttkrp(order, dim, t["idx"].T, t["val"], B)
+        assert rel_err(C, full) <= TOL_BF16_E2E

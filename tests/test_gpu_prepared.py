@@ -319,33 +319,3 @@ def test_prepared_mttkrp_lds_rejects_large_index_space():
     want, _ = oracle.mttkrp(3, 100000, t["idx"].T, f32(t["val"]), f32(Bh))
     assert rel_err(C.cpu().numpy(), want) <= TOL32
     T.close()
-
-
-def test_prepared_full_size_ssymv_rmat():
-    m = synth.workload("ssymv_rmat")
-    A = systec.Tensor.from_csr(dev(m["rowptr"]), dev(m["col"]), dev(m["val"].astype(np.float32)))
-    for xdtype in ("bf16", "f32"):
-        x, xref = _x(m, xdtype)
-        y = A.ssymv(x).cpu().numpy()
-        want, counts = oracle.ssymv(m["n"], m["rowptr"], m["col"], f32(m["val"]), xref)
-        assert rel_err(y, want) <= TOL32, xdtype
-    assert A.effective_nnz == counts["effective_nnz"]
-
-
-@pytest.mark.parametrize("name", ["mttkrp3", "mttkrp5"])
-def test_prepared_full_size_mttkrp_sampled(name):
-    t = synth.workload(name)
-    I = t["dim"]
-    T = systec.Tensor.from_coo([dev(a) for a in t["idx"]], dev(t["val"].astype(np.float32)), I)
-    rng = np.random.Generator(np.random.PCG64(6))
-    rows = np.unique(np.concatenate([[0, I - 1], rng.integers(0, I, 200)]))
-    mask = np.zeros(I, np.uint8)
-    mask[rows] = 1
-    Bd = systec.quantize_bf16(dev(t["B"].astype(np.float32)))
-    want, counts = oracle.mttkrp(t["order"], I, t["idx"].T, f32(t["val"]),
-                                 oracle.round_bf16(t["B"].astype(np.float32)), row_mask=mask)
-    algos = ["views", "atomic"] + (["lds"] if name == "mttkrp5" else [])
-    for algo in algos:  # the launch configurations the benchmark times
-        C = T.mttkrp(Bd, algo=algo).cpu().numpy()
-        assert rel_err(C[rows], want[rows]) <= TOL32, algo
-    assert T.effective_nnz == counts["effective_nnz"]

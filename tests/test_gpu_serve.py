@@ -59,6 +59,8 @@ def _requests(mats, tens, count, seed):
 
 
 def _submit(srv, ids, mats, tens, req, bf16):
+    """Submits without synchronizing: the request is ordered after the
+    current stream, which wrote its input."""
     import torch
     p, inp, R = req
     x = dev(inp.astype(np.float32))
@@ -68,7 +70,6 @@ def _submit(srv, ids, mats, tens, req, bf16):
         out = torch.empty(mats[p]["n"], device="cuda")
     else:
         out = torch.empty((tens[p - len(mats)]["dim"], R), device="cuda")
-    torch.cuda.synchronize()  # inputs ready before the server's stream reads them
     return srv.submit(ids[p], x, out), out
 
 
@@ -246,3 +247,32 @@ def test_unknown_ids_and_timeout():
         with pytest.raises(systec.SystecError) as e:
             srv.wait(12345, 10)
         assert e.value.status_name == "SYSTEC_ENOTFOUND"
+
+
+def test_submit_waits_for_the_callers_stream():
+    """A request submitted right after slow work on the caller's stream that
+    writes its input and last uses its output buffer: the server's stream
+    waits for that work (no host synchronization in between)."""
+    import torch
+    mats, tens = _pool()
+    reqs = _requests(mats, tens, 6, seed=9)
+    big = torch.rand((4096, 4096), device="cuda")
+    with systec.Server(budget_bytes=8 << 30, max_slots=8, step_work_nnz=1 << 17) as srv:
+        ids = _register(srv, mats, tens)
+        torch.cuda.synchronize()
+        outs = []
+        for p, inp, R in reqs:
+            src = dev(inp.astype(np.float32))
+            torch.cuda.synchronize()
+            x = torch.empty_like(src)
+            out = torch.full((mats[p]["n"],) if p < len(mats) else (tens[p - len(mats)]["dim"], R),
+                             7.0, device="cuda")
+            for _ in range(8):  # slow work queued ahead of the input's write
+                big = torch.mm(big, big).clamp_(-1.0, 1.0)
+            out.fill_(3.0)  # the output buffer's last earlier use
+            x.copy_(src)
+            outs.append((srv.submit(ids[p], x, out), out, x))
+        for rid, _, _ in outs:
+            srv.wait(rid, 60_000_000)
+    for r, (_, o, _) in zip(reqs, outs):
+        assert rel_err(o.cpu().numpy(), _oracle(mats, tens, r, False)) <= TOL32
