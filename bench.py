@@ -92,6 +92,9 @@ def parse():
                          "record of its own in the same JSON line ('' for none)")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the non-symmetric comparison kernel")
+    ap.add_argument("--only-step", action="store_true",
+                    help="time the step alone (no cold runs, other paths, comparisons or "
+                         "errors): for profiler runs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="run one plain device copy of this many MiB first (scales the "
                          "HBM byte counters of a rocprofv3 --pmc run)")
@@ -262,7 +265,8 @@ def roofline(b_alg, k_ms, kernel_key, kernel_src, traffic_key, copy_gbs):
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": load_traffic(traffic_key, h, b_alg),
             "kernel": kernel_key, "kernel_ms": k_ms, "kernel_source_hash": h,
-            "copy_ceiling_gbs": copy_gbs, "frac_of_copy_ceiling": round(achieved / copy_gbs, 4)}
+            "copy_ceiling_gbs": copy_gbs,
+            "frac_of_copy_ceiling": round(achieved / copy_gbs, 4) if copy_gbs else None}
 
 
 def measure_ssymv(a, torch, systec, w, dev, flush, copy_gbs, with_cpu):
@@ -303,6 +307,9 @@ def measure_ssymv(a, torch, systec, w, dev, flush, copy_gbs, with_cpu):
     k_ms, _ = kernel_ms(step, max(10, a.steps))
     rec["roofline"] = roofline(b_alg, k_ms, kernel_key, kernel_src,
                                f"{kernel_key}:{a.workload}:{a.form}", copy_gbs)
+    if a.only_step:
+        A.close()
+        return rec
     rec["cold"] = cold_ms(torch, step, 20, flush)
     osec = timed(other, max(5, a.steps // 4), 2)
     rec["other_path"] = {"path": "oneshot" if a.path == "prepared" else "prepared",
@@ -442,6 +449,9 @@ def measure_mttkrp(a, torch, systec, w, name, dev, flush, copy_gbs, with_cpu, st
     k_ms, _ = kernel_ms(step, max(10, steps))
     rec["roofline"] = roofline(b_alg, k_ms, kernel_key, kernel_src,
                                f"{kernel_key}:{name}:{a.form}", copy_gbs)
+    if a.only_step:
+        T.close()
+        return rec
     rec["cold"] = cold_ms(torch, step, 20, flush)
     osec = timed(other, max(5, steps // 4), 2)
     rec["other_path"] = {"path": "oneshot" if a.path == "prepared" else "prepared",
@@ -530,7 +540,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst, fl
     flush = torch.empty(1 << 27, dtype=torch.float32, device=dev)  # 512 MiB
-    copy_gbs = copy_ceiling_gbs(torch, dev)
+    copy_gbs = None if a.only_step else copy_ceiling_gbs(torch, dev)
     with_cpu = not a.no_cpu
     t_gen = time.perf_counter()
     w = synth.workload(a.workload)
@@ -545,7 +555,7 @@ def main():
         rec = measure_mttkrp(a, torch, systec, w, a.workload, dev, flush, copy_gbs, with_cpu,
                              a.steps, a.warmup)
     rec.pop("unit", None)
-    rec["setup_s"]["generate"] = round(t_gen, 2)
+    rec.setdefault("setup_s", {})["generate"] = round(t_gen, 2)
     out.update(rec)
     del w
     # the other workloads, each in its own record of the same line
@@ -558,7 +568,7 @@ def main():
         r = measure_mttkrp(a, torch, systec, ws, name, dev, flush, copy_gbs, with_cpu,
                            max(10, a.steps), a.warmup)
         r["dtype"] = a.form
-        r["setup_s"]["generate"] = round(t_gen, 2)
+        r.setdefault("setup_s", {})["generate"] = round(t_gen, 2)
         out[name] = r
         del ws
     print(json.dumps(out), flush=True)
