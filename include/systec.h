@@ -103,6 +103,19 @@ SYSTEC_API int systec_syprd(int64_t n, int64_t nnz, const int32_t* rowptr, const
                  const float* val, const void* x, systec_dtype xdt, double* out,
                  systec_stream stream);
 
+/* systec_syprd that allocates nothing, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation). Arguments, result and errors as for
+ * systec_syprd; the per-workgroup partials live in a fixed 1 MiB array of
+ * the library, one per device, held until the process ends, so n + nnz may
+ * be at most 536,870,912 (2^29; larger: SYSTEC_EINVAL, nothing launched).
+ * Every call on a device uses that device's one array: calls that overlap
+ * on one device (different streams, threads) race and must be serialized
+ * by the caller. SYSTEC_VALIDATE is not applied here. */
+SYSTEC_API int systec_syprd_noalloc(int64_t n, int64_t nnz, const int32_t* rowptr,
+                                    const int32_t* col, const float* val, const void* x,
+                                    systec_dtype xdt, double* out, systec_stream stream);
+
 /* ------------------------------------------------------------------------
  * Bellman-Ford update  y[i] = min_j (A[i,j] + d[j])  (Sec. 5.2.2: A the
  * symmetric matrix of edge lengths, d the path lengths after k steps, y

@@ -31,6 +31,7 @@ SIGNATURES = {
     "systec_version": [],
     "systec_ssymv": [I64, I64, P, P, P, P, I32, P, P],
     "systec_syprd": [I64, I64, P, P, P, P, I32, P, P],
+    "systec_syprd_noalloc": [I64, I64, P, P, P, P, I32, P, P],
     "systec_bellman_ford": [I64, I64, P, P, P, P, P, P],
     "systec_bellman_ford_t": [P, P, P, P],
     "systec_cp_step": [P, P, I32, I64, P, P, P, P, P],

@@ -148,6 +148,15 @@ int systec_syprd(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* c
   return launch_syprd(n, nnz, rowptr, col, val, x, xdt, out, static_cast<hipStream_t>(stream));
 }
 
+int systec_syprd_noalloc(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col,
+                         const float* val, const void* x, systec_dtype xdt, double* out,
+                         systec_stream stream) {
+  const int rc = check_csr_args("systec_syprd_noalloc", n, nnz, rowptr, col, val, x, xdt, out);
+  if (rc) return rc;
+  return launch_syprd_noalloc(n, nnz, rowptr, col, val, x, xdt, out,
+                              static_cast<hipStream_t>(stream));
+}
+
 namespace {
 
 // Staging B in LDS is not chosen automatically: measured on the 5-D

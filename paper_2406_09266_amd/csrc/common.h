@@ -59,6 +59,11 @@ int launch_ssymv(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* c
 int launch_syprd(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col,
                  const float* val, const void* x, systec_dtype xdt, double* out,
                  hipStream_t s);
+// launch_syprd with its partials in the library's fixed per-device scratch
+// (allocates nothing; EINVAL when n + nnz exceeds what the scratch holds).
+int launch_syprd_noalloc(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col,
+                         const float* val, const void* x, systec_dtype xdt, double* out,
+                         hipStream_t s);
 int launch_mttkrp(int order, int64_t I, int64_t nnz, const int32_t* const* idx,
                   const float* val, const void* B, systec_dtype bdt, int64_t R, float* C,
                   bool symmetric, hipStream_t s);

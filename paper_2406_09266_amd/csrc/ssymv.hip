@@ -258,32 +258,91 @@ int launch_ssymv(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* c
                    : launch_csr_typed<uint16_t, false>(ni, nz, rowptr, col, val, xb, y, s);
 }
 
-int launch_syprd(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col,
-                 const float* val, const void* x, systec_dtype xdt, double* out,
-                 hipStream_t s) {
+namespace {
+
+int64_t syprd_blocks(int64_t n, int64_t nnz) {
   const int64_t tiles = (n + nnz + kTile - 1) / kTile;
-  const int64_t blocks = std::max<int64_t>(1, (tiles + kWaves - 1) / kWaves);
-  float* partial = nullptr;
-  int rc = check_hip(hipMallocAsync(reinterpret_cast<void**>(&partial), blocks * sizeof(float), s),
-                     "hipMallocAsync(syprd partials)");
-  if (rc != SYSTEC_OK) return rc;
+  return std::max<int64_t>(1, (tiles + kWaves - 1) / kWaves);
+}
+
+// The one-shot SYPRD into `partial` (one FP32 partial per workgroup, every
+// one written) and its FP64 final sum.
+int syprd_into(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col,
+               const float* val, const void* x, systec_dtype xdt, double* out, float* partial,
+               hipStream_t s) {
+  const int64_t blocks = syprd_blocks(n, nnz);
   const int ni = static_cast<int>(n), nz = static_cast<int>(nnz);
-  {
-    LaunchTimer timer(s);
-    if (xdt == SYSTEC_F32)
-      syprd_tiles_kernel<float><<<dim3(blocks), dim3(kBlock), 0, s>>>(
-          ni, nz, rowptr, col, val, static_cast<const float*>(x), partial);
-    else
-      syprd_tiles_kernel<uint16_t><<<dim3(blocks), dim3(kBlock), 0, s>>>(
-          ni, nz, rowptr, col, val, static_cast<const uint16_t*>(x), partial);
-    rc = check_launch("syprd kernel");
-  }
+  if (xdt == SYSTEC_F32)
+    syprd_tiles_kernel<float><<<dim3(blocks), dim3(kBlock), 0, s>>>(
+        ni, nz, rowptr, col, val, static_cast<const float*>(x), partial);
+  else
+    syprd_tiles_kernel<uint16_t><<<dim3(blocks), dim3(kBlock), 0, s>>>(
+        ni, nz, rowptr, col, val, static_cast<const uint16_t*>(x), partial);
+  int rc = check_launch("syprd kernel");
   if (rc == SYSTEC_OK) {
     reduce_partials_f64<<<dim3(1), dim3(1024), 0, s>>>(partial, static_cast<int>(blocks), out);
     rc = check_launch("syprd final reduction");
   }
+  return rc;
+}
+
+// The scratch of the allocation-free SYPRD (systec_syprd_noalloc): room for
+// the per-workgroup partials of n + nnz <= kNoAllocItems. Each device holds
+// its own copy for the life of the process; in host code its name is only a
+// stand-in, so kernels get the address from hipGetSymbolAddress.
+constexpr int64_t kNoAllocPartials = int64_t(1) << 18;  // 1 MiB of FP32
+constexpr int64_t kNoAllocItems = kNoAllocPartials * kTile * kWaves;
+__device__ __align__(256) float scratch[kNoAllocPartials];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+
+// The address of the current device's copy of `scratch`, looked up once
+// per device with that device current.
+int scratch_address(float** out) {
+  int dev = 0;
+  int rc = check_hip(hipGetDevice(&dev), "hipGetDevice");
+  if (rc) return rc;
+  if (dev < 0 || dev >= kMaxDevices) return fail(SYSTEC_EINVAL, "device ordinal out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    rc = check_hip(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (rc) return rc;
+    g_scratch_ptr[dev] = static_cast<float*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return SYSTEC_OK;
+}
+
+}  // namespace
+
+int launch_syprd(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col,
+                 const float* val, const void* x, systec_dtype xdt, double* out,
+                 hipStream_t s) {
+  const int64_t blocks = syprd_blocks(n, nnz);
+  float* partial = nullptr;
+  int rc = check_hip(hipMallocAsync(reinterpret_cast<void**>(&partial), blocks * sizeof(float), s),
+                     "hipMallocAsync(syprd partials)");
+  if (rc != SYSTEC_OK) return rc;
+  {
+    LaunchTimer timer(s);
+    rc = syprd_into(n, nnz, rowptr, col, val, x, xdt, out, partial, s);
+  }
   const int rc2 = check_hip(hipFreeAsync(partial, s), "hipFreeAsync(syprd partials)");
   return rc != SYSTEC_OK ? rc : rc2;
+}
+
+int launch_syprd_noalloc(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col,
+                         const float* val, const void* x, systec_dtype xdt, double* out,
+                         hipStream_t s) {
+  if (n + nnz > kNoAllocItems)
+    return fail(SYSTEC_EINVAL, "systec_syprd_noalloc: n + nnz exceeds the fixed scratch (" +
+                                   std::to_string(kNoAllocItems) + ")");
+  float* partial = nullptr;
+  const int rc = scratch_address(&partial);
+  return rc ? rc : syprd_into(n, nnz, rowptr, col, val, x, xdt, out, partial, s);
 }
 
 namespace {
