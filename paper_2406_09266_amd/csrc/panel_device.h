@@ -10,11 +10,15 @@ namespace dev {
 
 // SSYMV over one chunk (tiles [tb, te) of panel p) of a matrix in the panel
 // format (see plan.hip), by the whole workgroup, which it synchronizes. The
-// panel's row sums live in LDS as FP32 (s_rows, H of them), added with LDS
-// FP32 atomics (ds_add_f32) and flushed to y once per chunk. On gfx950 these
-// run at about a tenth of the rate of integer and FP64 LDS atomics (measured
-// 0.2 T/s for the device), and every stored entry makes one, so they bound
-// the kernel; a compare-and-swap loop on the LDS word was measured no faster.
+// panel's row sums live in LDS as FP32 (s_rows, H of them) and are flushed
+// to y once per chunk. A row-side update is a compare-and-swap on the LDS
+// word (read, add, ds_cmpst), which runs at the integer LDS atomic rate;
+// gfx950 runs the LDS FP32 add (ds_add_f32) at about a tenth of that rate.
+// A tile's attempts go out back to back before its column-side work and are
+// checked after it, so their LDS round trip overlaps that work; an attempt
+// that lost a race (another lane or wave changed the word in between, which
+// happens on the hub rows) is finished with one ds_add_f32, so contended
+// rows take the FP32 add and the rest take the integer pipeline.
 // The entries arrive sorted
 // by column and are taken lane-strided (step k of a wave holds 64 consecutive
 // entries), so the column-side updates y[j] += a x[i] reduce across the wave
@@ -66,10 +70,22 @@ __device__ __forceinline__ void ssymv_panel_chunk(int n, int H, int p, int tb, i
       xc[k] = load_f32(x, c[k]);
       xr[k] = kStageX ? load_f32(s_x, ro[k]) : load_f32(x, r0 + ro[k]);
     }
-    // row side, y[i] += a x[j] (padding entries have a = 0)
+    // row side, y[i] += a x[j]: first compare-and-swap attempts, issued
+    // without a branch so that they leave back to back (a zero product
+    // swaps a word for itself)
+    unsigned* const s_bits = reinterpret_cast<unsigned*>(s_rows);
+    float rv[kV];
+    unsigned seen[kV];
+    unsigned got[kV];
+#pragma unroll
+    for (int k = 0; k < kV; ++k) {
+      rv[k] = a[k] * xc[k];
+      seen[k] = s_bits[ro[k]];
+    }
 #pragma unroll
     for (int k = 0; k < kV; ++k)
-      if (a[k] != 0.0f) atomicAdd(s_rows + ro[k], a[k] * xc[k]);
+      got[k] = atomicCAS(s_bits + ro[k], seen[k],
+                         __float_as_uint(__uint_as_float(seen[k]) + rv[k]));
     int carry_key = -1;
     float carry = 0.0f;
 #pragma unroll
@@ -90,6 +106,15 @@ __device__ __forceinline__ void ssymv_panel_chunk(int n, int H, int p, int tb, i
       if (ends && seg != 0.0f) atomic_add_noret(y + c[k], seg);
       carry_key = __builtin_amdgcn_readlane(c[k], kWave - 1);
       carry = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(seg), kWave - 1));
+    }
+    // row side: an attempt that lost a race (another lane or wave changed the
+    // word in between; mostly the hub rows) is finished with the LDS FP32 add
+#pragma unroll
+    for (int k = 0; k < kV; ++k) {
+      // the empty asm pins the check (and its wait for the attempt's result)
+      // here, after the column side, instead of between the attempts
+      asm volatile("" : "+v"(got[k])::"memory");
+      if (got[k] != seen[k]) atomicAdd(s_rows + ro[k], rv[k]);
     }
     if (lane == 0 && carry != 0.0f) atomic_add_noret(y + carry_key, carry);
   }
