@@ -200,16 +200,20 @@ SYSTEC_API int systec_mttkrp_partial(int order, int nparts, const int32_t* part_
 /* ------------------------------------------------------------------------
  * How the updates of the non-leading slots are resolved (all give the same
  * result up to FP32 summation order):
- *   SYSTEC_MTTKRP_AUTO     the library chooses from I, R and the dtype
+ *   SYSTEC_MTTKRP_AUTO     the library chooses from I, R and the dtype (and,
+ *                          for a prepared tensor, the lengths of its runs)
  *   SYSTEC_MTTKRP_ATOMIC   canonical list; leading slot summed in registers
  *                          across a run of equal c1 (Sec. 4.2.8), the other
  *                          run-start slots by device FP32 atomics
- *   SYSTEC_MTTKRP_LDS      slot views of a prepared tensor with the factor
- *                          rows staged in LDS by column slices (prepared
- *                          tensors of small index spaces: a slice of one
- *                          16-byte vector per row, 8 BF16 or 4 FP32 columns,
- *                          must fit one workgroup's LDS; with 160 KiB that
- *                          is I <= 10,220); otherwise EINVAL
+ *   SYSTEC_MTTKRP_LDS      slot views of a prepared tensor with B staged in
+ *                          LDS: all of B with one lane per view entry when
+ *                          I * R elements fit one workgroup's LDS (160 KiB:
+ *                          I = 5,000 at R = 16 in BF16), R is 16 or 32 (or
+ *                          8 in BF16), B is 16-byte aligned and the tensor
+ *                          holds at least 64 entries per index; else column
+ *                          slices of B (a slice of one 16-byte vector per
+ *                          row, 8 BF16 or 4 FP32 columns, must fit: with
+ *                          160 KiB that is I <= 10,220); otherwise EINVAL
  *   SYSTEC_MTTKRP_VIEWS    slot views of a prepared tensor (systec_mttkrp_t
  *                          only; EINVAL for the one-shot call)
  * ---------------------------------------------------------------------- */
@@ -221,8 +225,11 @@ typedef enum {
 } systec_mttkrp_algo;
 
 /* The algorithm AUTO runs for this shape: *algo receives ATOMIC for a
- * one-shot call (prepared == 0), VIEWS for a prepared
- * tensor. Errors: EINVAL (NULL algo, I or R out of range, bad dtype). */
+ * one-shot call (prepared == 0); for a prepared tensor LDS when all of B
+ * fits one workgroup's LDS with R 16 or 32 (or 8 in BF16), else VIEWS. A
+ * prepared tensor with fewer than 64 entries per index, or a B that is not
+ * 16-byte aligned, runs the views under AUTO even where LDS is reported.
+ * Errors: EINVAL (NULL algo, I or R out of range, bad dtype). */
 SYSTEC_API int systec_mttkrp_choose(int64_t I, systec_dtype bdt, int64_t R, int prepared,
                                     systec_mttkrp_algo* algo);
 
@@ -434,7 +441,7 @@ SYSTEC_API int systec_cp_step(const systec_tensor* t, const void* B, systec_dtyp
                               int64_t R, float* C, float* B_new, float* G, double* fit,
                               systec_stream stream);
 /* systec_mttkrp_t with an explicit algorithm (systec_mttkrp_t is AUTO: the
- * slot views).
+ * one-lane-per-entry LDS form where it applies, else the slot views).
  * ATOMIC runs on the tensor's canonical list (its first view). */
 SYSTEC_API int systec_mttkrp_t_ex(const systec_tensor* t, const void* B, systec_dtype bdt,
                                   int64_t R, float* C, systec_mttkrp_algo algo,

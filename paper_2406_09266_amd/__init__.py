@@ -419,8 +419,9 @@ class Tensor:
 
     def mttkrp(self, B, out=None, stream=None, algo="auto"):
         """C = MTTKRP of the prepared tensor; algo: "auto", "views" (slot
-        views), "lds" (slot views with B staged in LDS; small index spaces)
-        or "atomic" (the canonical list with device atomics)."""
+        views), "lds" (slot views with B staged in LDS; small index spaces;
+        the automatic choice where all of B fits) or "atomic" (the canonical
+        list with device atomics)."""
         torch = _torch()
         _dev(B, None, "B")
         I, R = B.shape

@@ -159,12 +159,13 @@ int systec_syprd_noalloc(int64_t n, int64_t nnz, const int32_t* rowptr, const in
 
 namespace {
 
-// Staging B in LDS is not chosen automatically: measured on the 5-D
-// workload (I = 5,000, R = 16) it is slower than the slot views (1.16 ms
-// against 0.83 ms), because each lane group walks its own contiguous range,
-// so an index load touches one cache line per group and the index streams
-// are re-read from L2 instead of L1.
-bool lds_preferred(int64_t, systec_dtype, int64_t) { return false; }
+// A prepared tensor whose whole factor fits one workgroup's LDS takes the
+// one-lane-per-entry form with B in LDS: on the 5-D workload (I = 5,000,
+// R = 16, BF16) it runs in 0.26 ms against 0.48 ms for the views, whose
+// lane groups gather the factor rows through the L1.
+bool lds_preferred(int64_t I, systec_dtype bdt, int64_t R) {
+  return mttkrp_lane_shape_fits(I, bdt, R);
+}
 
 }  // namespace
 
@@ -559,8 +560,13 @@ int systec_mttkrp_t_ex(const systec_tensor* t, const void* B, systec_dtype bdt, 
   if (algo < SYSTEC_MTTKRP_AUTO || algo > SYSTEC_MTTKRP_VIEWS)
     return fail(SYSTEC_EINVAL, "systec_mttkrp_t: unknown algorithm");
   auto s = static_cast<hipStream_t>(stream);
-  if (algo == SYSTEC_MTTKRP_AUTO)
-    algo = lds_preferred(tn->dim, bdt, R) ? SYSTEC_MTTKRP_LDS : SYSTEC_MTTKRP_VIEWS;
+  if (algo == SYSTEC_MTTKRP_AUTO) {
+    if (lds_preferred(tn->dim, bdt, R)) {
+      rc = launch_mttkrp_views_lane(tn, B, bdt, R, C, s);
+      if (rc != -1) return rc;  // else the tensor's runs are short: the views
+    }
+    algo = SYSTEC_MTTKRP_VIEWS;
+  }
   if (algo == SYSTEC_MTTKRP_VIEWS) return launch_mttkrp_views(tn, B, bdt, R, C, s);
   if (algo == SYSTEC_MTTKRP_LDS) return launch_mttkrp_views_lds(tn, B, bdt, R, C, s);
   // the first view holds every entry in canonical order

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -149,11 +150,35 @@ struct Tensor {
   bool short_runs = false;
   int32_t* vidx[5][5] = {};
   float* vval[5] = {};
+  // Packed views for the one-lane-per-entry MTTKRP with B in LDS, built
+  // when that form can apply (I * 16 bytes fits one workgroup's LDS, so I <
+  // 65,536, and the runs are long): view t as records of lane_words 32-bit
+  // words, ceil(N/2) words of two 16-bit indices (slot 2q in the low half)
+  // and then coef[mask][t] * v in FP32; each view padded to a multiple of 64
+  // records of weight 0 whose output index is the view's last one.
+  uint32_t* lview[5] = {};
+  int64_t lnnz[5] = {0, 0, 0, 0, 0};  // padded record counts
+  int lane_words = 0;
   // serving (built at registration)
   ServeTensor* d_serve = nullptr;
   ServeUnit* d_units = nullptr;
   std::vector<void*> allocations;
 };
+// Device memory owned by a prepared operand (freed with it, counted in its
+// bytes).
+template <typename T>
+int tensor_alloc(Tensor* t, T** p, size_t count) {
+  void* q = nullptr;
+  const size_t bytes = std::max<size_t>(1, count) * sizeof(T);
+  hipError_t e = hipMalloc(&q, bytes);
+  if (e != hipSuccess)
+    return fail(SYSTEC_ENOMEM, std::string("hipMalloc (prepared operand): ") + hipGetErrorString(e));
+  t->allocations.push_back(q);
+  t->bytes += bytes;
+  *p = static_cast<T*>(q);
+  return SYSTEC_OK;
+}
+
 // Holds a prepared matrix's work buffers for one call: the host lock while
 // the call enqueues, and on the device the call's stream waits for the
 // previous holder's work (any stream) and marks the end of its own.
@@ -226,6 +251,18 @@ int launch_cp_step(const Tensor* t, const void* B, systec_dtype bdt, int64_t R, 
                    float* B_new, float* G, double* fit, hipStream_t s);
 int launch_mttkrp_views_lds(const Tensor* t, const void* B, systec_dtype bdt, int64_t R, float* C,
                             hipStream_t s);
+// One lane per view entry with all of B staged in LDS (mttkrp_lane.hip);
+// -1 (nothing launched) unless B fits one workgroup's LDS, R is 8 (BF16), 16
+// or 32 and the tensor's runs are long.
+int launch_mttkrp_views_lane(const Tensor* t, const void* B, systec_dtype bdt, int64_t R,
+                             float* C, hipStream_t s);
+// Builds the packed views (Tensor::lview) of a tensor whose views exist, if
+// the one-lane-per-entry form can apply to it; else leaves them empty.
+int build_lane_views(Tensor* t, hipStream_t s);
+// Whether the one-lane-per-entry form applies to this shape (B fits one
+// workgroup's LDS, R is 8 in BF16, 16 or 32); the tensor's runs decide the
+// rest.
+bool mttkrp_lane_shape_fits(int64_t I, systec_dtype bdt, int64_t R);
 
 // ---- serving step (serve_kernel.hip) ----------------------------------------
 // A prepared operand as the serving kernels see it (device memory, built when

@@ -353,6 +353,10 @@ int mttkrp_lds_width(int64_t I, systec_dtype bdt, int64_t R) {
 
 int launch_mttkrp_views_lds(const Tensor* t, const void* B, systec_dtype bdt, int64_t R, float* C,
                             hipStream_t s) {
+  // all of B in LDS with one lane per view entry where it fits, else
+  // column slices of B
+  const int lrc = launch_mttkrp_views_lane(t, B, bdt, R, C, s);
+  if (lrc != -1) return lrc;
   int rc = launch_fill_f32(C, t->dim * R, s);
   if (rc != SYSTEC_OK || t->nnz == 0) return rc;
   const int r = static_cast<int>(R);

@@ -226,18 +226,6 @@ struct Scratch {
   }
 };
 
-template <typename T>
-int tensor_alloc(Tensor* t, T** p, size_t count) {
-  void* q = nullptr;
-  const size_t bytes = std::max<size_t>(1, count) * sizeof(T);
-  hipError_t e = hipMalloc(&q, bytes);
-  if (e != hipSuccess) return fail(SYSTEC_ENOMEM, std::string("hipMalloc (prepared operand): ") + hipGetErrorString(e));
-  t->allocations.push_back(q);
-  t->bytes += bytes;
-  *p = static_cast<T*>(q);
-  return SYSTEC_OK;
-}
-
 template <typename K>
 int radix_sort_pairs(const K* kin, K* kout, const uint32_t* vin, uint32_t* vout, int n,
                      int end_bit, hipStream_t s) {
@@ -513,6 +501,8 @@ int tensor_create_coo(int order, int64_t I, int64_t nnz, const int32_t* const* i
       if ((rc = check_hip(hipStreamSynchronize(s), "hipStreamSynchronize"))) break;
     }
   }
+  if (!rc) rc = build_lane_views(t, s);
+  if (!rc) rc = check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
   if (rc) {
     tensor_free(t);
     return rc;

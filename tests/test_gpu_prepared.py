@@ -7,7 +7,7 @@ import oracle
 import paper_2406_09266_amd as systec
 from paper_2406_09266_amd import synth
 
-from gpu_util import dev, f32, rel_err
+from gpu_util import assert_elementwise, dev, f32, rel_err
 
 pytestmark = pytest.mark.gpu
 TOL32 = 1e-5
@@ -261,6 +261,9 @@ def test_prepared_mttkrp_short_runs(order, dim, nnz, R, bdtype):
     C = T.mttkrp(Bd, algo="views").cpu().numpy()
     want, _ = oracle.mttkrp(order, dim, t["idx"].T, f32(t["val"]), Bref)
     assert rel_err(C, want) <= TOL32
+    # where all of B fits LDS the automatic choice would take the lane form,
+    # which short runs exclude: it falls back to the views
+    assert rel_err(T.mttkrp(Bd).cpu().numpy(), want) <= TOL32
     T.close()
 
 
@@ -283,9 +286,12 @@ def test_prepared_mttkrp_all_diagonal(order):
     (3, 2000, 100, "bf16"),   # two 64-column slices, ragged last slice
     (4, 600, 40, "f32"),      # FP32 B, one 64-column slice (40 used)
     (5, 30, 16, "f32"),       # fewer entries than workgroups x lane groups
+    (4, 1200, 32, "f32"),     # all of B in LDS (153,600 B), FP32, 32 columns
+    (3, 3000, 16, "f32"),     # all of B in LDS, views ending inside a wave tile
 ])
 def test_prepared_mttkrp_lds_shapes(order, dim, R, bdtype):
-    nnz = {5000: 200003, 10000: 150001, 9000: 120007, 2000: 50021, 600: 40009, 30: 3001}[dim]
+    nnz = {5000: 200003, 10000: 150001, 9000: 120007, 2000: 50021, 600: 40009, 30: 3001,
+           1200: 90017, 3000: 200019}[dim]
     t = synth.sym_coo(order, dim, nnz, repeat_frac=0.05, seed=2000 + dim)
     B = synth.dense_uniform((dim, R), seed=dim)
     print(f"prepared mttkrp lds order={order} dim={dim} nnz={nnz} R={R} B={bdtype}", flush=True)
@@ -296,8 +302,41 @@ def test_prepared_mttkrp_lds_shapes(order, dim, R, bdtype):
         Bd = systec.quantize_bf16(Bd)
         Bref = oracle.round_bf16(B.astype(np.float32))
     want, _ = oracle.mttkrp(order, dim, t["idx"].T, f32(t["val"]), Bref)
-    assert rel_err(T.mttkrp(Bd, algo="lds").cpu().numpy(), want) <= TOL32
-    assert rel_err(T.mttkrp(Bd, algo="views").cpu().numpy(), want) <= TOL32
+    scale, _ = oracle.mttkrp(order, dim, t["idx"].T, np.abs(f32(t["val"])), np.abs(Bref))
+    for algo in ("lds", "views", "auto"):
+        C = T.mttkrp(Bd, algo=algo).cpu().numpy()
+        assert_elementwise(C, want, scale, TOL32, f"lds shape {algo}")
+        assert rel_err(C, want) <= TOL32
+    T.close()
+
+
+@pytest.mark.parametrize("special", ["none", "tiny", "huge"])
+@pytest.mark.parametrize("order", [3, 5])
+def test_prepared_mttkrp_lane_form_half_staging(order, special):
+    """The one-lane-per-entry form with a BF16 factor: staged as FP16 when
+    every value converts exactly, as BF16 when one does not (a value below
+    2^-17 or above 65,504); both against the oracle, element by element."""
+    dim, R = 900, 16
+    t = synth.sym_coo(order, dim, 120011, repeat_frac=0.1, seed=77 + order)
+    B = synth.dense_uniform((dim, R), seed=78)
+    B[B == 0] = 0.5
+    B = np.where(np.abs(B) < 1e-3, 1e-3, B)  # all in FP16's exact range ...
+    if special == "tiny":
+        B[17, 3] = 3.0e-7  # ... except one value
+    elif special == "huge":
+        B[dim - 1, R - 1] = -1.5e5
+    Bref = oracle.round_bf16(B.astype(np.float32))
+    with np.errstate(over="ignore"):
+        exact = np.all(Bref.astype(np.float16).astype(np.float32) == Bref)
+    assert exact == (special == "none")
+    print(f"lane form order={order} special={special}", flush=True)
+    T = systec.Tensor.from_coo([dev(a) for a in t["idx"]], dev(t["val"].astype(np.float32)), dim)
+    Bd = systec.quantize_bf16(dev(B.astype(np.float32)))
+    want, _ = oracle.mttkrp(order, dim, t["idx"].T, f32(t["val"]), Bref)
+    scale, _ = oracle.mttkrp(order, dim, t["idx"].T, np.abs(f32(t["val"])), np.abs(Bref))
+    for algo in ("lds", "auto"):
+        C = T.mttkrp(Bd, algo=algo).cpu().numpy()
+        assert_elementwise(C, want, scale, TOL32, f"lane form {special} {algo}")
     T.close()
 
 
@@ -312,7 +351,9 @@ def test_prepared_mttkrp_lds_rejects_large_index_space():
         T.mttkrp(B, algo="lds")
     assert e.value.status_name == "SYSTEC_EINVAL"
     assert systec.mttkrp_choose(100000, 16, False, True) == "views"
-    assert systec.mttkrp_choose(5000, 16, True, True) == "views"
+    assert systec.mttkrp_choose(5000, 16, True, True) == "lds"  # all of B fits LDS
+    assert systec.mttkrp_choose(5000, 16, False, True) == "views"  # 320,000 B does not
+    assert systec.mttkrp_choose(5000, 12, True, True) == "views"  # R outside 8, 16, 32
     assert systec.mttkrp_choose(5000, 16, True, False) == "atomic"
     C = T.mttkrp(B)  # the automatic choice falls back to the views
     torch.cuda.synchronize()
