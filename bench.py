@@ -436,7 +436,7 @@ def measure_mttkrp(a, torch, systec, w, name, dev, flush, copy_gbs, with_cpu, st
     kernel_key = f"mttkrp{order}_{algo}" + ("" if a.path == "prepared" else "_oneshot")
     kernel_src = {"views": ("mttkrp.hip", "mttkrp_device.h", "plan.hip"),
                   "atomic": ("mttkrp.hip", "mttkrp_device.h"),
-                  "lds": ("mttkrp_lane.hip", "mttkrp_lds.hip", "mttkrp_device.h", "plan.hip")}[algo]
+                  "lds": ("mttkrp_lane.hip", "mttkrp_lds.hip", "mttkrp_device.h", "wave_ops.h", "plan.hip")}[algo]
     rec = {"config": {"workload": name, "order": order, "I": I, "R": R, "stored_nnz": nnz,
                       "effective_nnz": eff, "pattern_hist": hist, "B_storage": a.form,
                       "accumulate": "f32", "path": a.path, "algo": algo, "B_alg_bytes": b_alg}}
