@@ -123,6 +123,17 @@ struct Tensor {
   // value 0, which is no contribution to a sum but is one to a minimum)
   int32_t* chunk_valid_end = nullptr;
   std::vector<int32_t> h_chunk_panel, h_chunk_tile_begin, h_chunk_tile_end;  // host copies
+  // Column segments of the panel SSYMV: the maximal runs of equal column
+  // inside each 512-entry tile, numbered in entry order (tile t's segments
+  // are [seg_tile0[t], seg_tile0[t + 1])). The kernel writes one FP32 sum per
+  // segment to work_seg instead of adding it to y with an atomic, and a
+  // second pass adds each column's segments, listed by column in
+  // seg_ids[seg_colptr[c] .. seg_colptr[c + 1]) (in segment order).
+  int64_t nsegs = 0;
+  int32_t* seg_tile0 = nullptr;
+  int32_t* seg_colptr = nullptr;
+  int32_t* seg_ids = nullptr;
+  float* work_seg = nullptr;
   // vertex relabeling (matrix prepared with its vertices ordered by degree):
   // the panels hold P A P^T; perm[new] = old, inv[old] = new
   bool relabeled = false;

@@ -31,13 +31,20 @@ namespace dev {
 // the row-side gathers x[i] read LDS: their rows are scattered over the
 // panel, so from global memory each such wave load touches up to 64 cache
 // lines and the L1 tag lookups, not HBM, set the pace.
-template <typename XT, bool kStageX = false>
+// With kTwoPhase a segment total is not added to y: segment k of tile t (the
+// k-th run of equal columns in the tile, in entry order) is stored to
+// seg_out[seg_tile0[t] + k], and a second pass adds each column's segments.
+// The stores of one step go to consecutive words, where the atomics went to
+// scattered cache lines, each resolved at the memory side.
+template <typename XT, bool kStageX = false, bool kTwoPhase = false>
 __device__ __forceinline__ void ssymv_panel_chunk(int n, int H, int p, int tb, int te,
                                                   const int32_t* __restrict__ pcol,
                                                   const uint16_t* __restrict__ prow,
                                                   const float* __restrict__ pval,
                                                   const XT* __restrict__ x, float* __restrict__ y,
-                                                  float* s_rows, XT* s_x = nullptr) {
+                                                  float* s_rows, XT* s_x = nullptr,
+                                                  const int32_t* __restrict__ seg_tile0 = nullptr,
+                                                  float* __restrict__ seg_out = nullptr) {
   const int r0 = p * H;
   for (int i = threadIdx.x; i < H; i += blockDim.x) s_rows[i] = 0.0f;
   if constexpr (kStageX) {
@@ -88,6 +95,10 @@ __device__ __forceinline__ void ssymv_panel_chunk(int n, int H, int p, int tb, i
                          __float_as_uint(__uint_as_float(seen[k]) + rv[k]));
     int carry_key = -1;
     float carry = 0.0f;
+    // two-phase: the tile's first segment slot and the segments written so
+    // far (wave-uniform)
+    const int seg0 = kTwoPhase ? __builtin_amdgcn_readfirstlane(seg_tile0[tile]) : 0;
+    int nseg = 0;
 #pragma unroll
     for (int k = 0; k < kV; ++k) {
       const int r = r0 + ro[k];
@@ -95,7 +106,14 @@ __device__ __forceinline__ void ssymv_panel_chunk(int n, int H, int p, int tb, i
       // the previous step's last segment either continues in lane 0 here or
       // is complete and must be written now
       if (__builtin_amdgcn_readlane(c[k], 0) != carry_key) {
-        if (lane == 0 && carry != 0.0f) atomic_add_noret(y + carry_key, carry);
+        if constexpr (kTwoPhase) {
+          if (carry_key != -1) {
+            if (lane == 0) seg_out[seg0 + nseg] = carry;
+            ++nseg;
+          }
+        } else {
+          if (lane == 0 && carry != 0.0f) atomic_add_noret(y + carry_key, carry);
+        }
         carry_key = -1;
         carry = 0.0f;
       }
@@ -103,7 +121,15 @@ __device__ __forceinline__ void ssymv_panel_chunk(int n, int H, int p, int tb, i
       if (c[k] == carry_key) seg += carry;  // only lanes of the first segment match
       const int next_key = next_lane_i32(c[k], -1);
       const bool ends = lane != kWave - 1 && next_key != c[k];
-      if (ends && seg != 0.0f) atomic_add_noret(y + c[k], seg);
+      if constexpr (kTwoPhase) {
+        const uint64_t m = __ballot(ends);
+        const int below = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0));
+        if (ends) seg_out[seg0 + nseg + below] = seg;
+        nseg += __popcll(m);
+      } else {
+        if (ends && seg != 0.0f) atomic_add_noret(y + c[k], seg);
+      }
       carry_key = __builtin_amdgcn_readlane(c[k], kWave - 1);
       carry = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(seg), kWave - 1));
     }
@@ -116,7 +142,11 @@ __device__ __forceinline__ void ssymv_panel_chunk(int n, int H, int p, int tb, i
       asm volatile("" : "+v"(got[k])::"memory");
       if (got[k] != seen[k]) atomicAdd(s_rows + ro[k], rv[k]);
     }
-    if (lane == 0 && carry != 0.0f) atomic_add_noret(y + carry_key, carry);
+    if constexpr (kTwoPhase) {
+      if (lane == 0) seg_out[seg0 + nseg] = carry;  // the tile's last segment
+    } else {
+      if (lane == 0 && carry != 0.0f) atomic_add_noret(y + carry_key, carry);
+    }
   }
   __syncthreads();
   for (int i = threadIdx.x; i < H; i += blockDim.x) {

@@ -175,6 +175,38 @@ __global__ void panel_pad_kernel(int npanels, int H, const int32_t* __restrict__
   }
 }
 
+__global__ void iota_kernel(int64_t n, uint32_t* __restrict__ out) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    out[i] = static_cast<uint32_t>(i);
+}
+
+// ---- column segments of the panel SSYMV ----
+// flag[e] = 1 where a segment starts: at a tile's first entry or where the
+// column changes.
+__global__ void seg_flag_kernel(int64_t ppos, const int32_t* __restrict__ pcol,
+                                uint32_t* __restrict__ flag) {
+  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < ppos;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    flag[e] = (e % kPanelTile == 0 || pcol[e] != pcol[e - 1]) ? 1u : 0u;
+}
+
+// Segment s's column and each tile's first segment; counts segments per
+// column.
+__global__ void seg_fill_kernel(int64_t ppos, const int32_t* __restrict__ pcol,
+                                const uint32_t* __restrict__ flag,
+                                const uint32_t* __restrict__ first, uint32_t* __restrict__ seg_col,
+                                int32_t* __restrict__ tile0, uint32_t* __restrict__ col_count) {
+  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < ppos;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    if (flag[e]) {
+      seg_col[first[e]] = static_cast<uint32_t>(pcol[e]);
+      atomicAdd(col_count + pcol[e], 1u);
+    }
+    if (e % kPanelTile == 0) tile0[e / kPanelTile] = static_cast<int32_t>(first[e]);
+  }
+}
+
 // ---- slot views ----
 __global__ void view_keys_kernel(int order, int t, int nnz, const int32_t* i0, const int32_t* i1,
                                  const int32_t* i2, const int32_t* i3, const int32_t* i4,
@@ -244,6 +276,19 @@ int radix_sort_pairs(const K* kin, K* kout, const uint32_t* vin, uint32_t* vout,
   return rc;
 }
 
+int exclusive_sum(const uint32_t* in, uint32_t* out, int n, hipStream_t s) {
+  size_t tmp_bytes = 0;
+  int rc = check_hip(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, in, out, n, s),
+                     "exclusive scan (size)");
+  if (rc) return rc;
+  Scratch sc;
+  unsigned char* tmp = nullptr;
+  if ((rc = sc.alloc(&tmp, tmp_bytes))) return rc;
+  rc = check_hip(hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, in, out, n, s), "exclusive scan");
+  if (!rc) rc = check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+  return rc;
+}
+
 int bits_for(int64_t v) {
   int b = 0;
   while ((int64_t(1) << b) < v) ++b;
@@ -309,6 +354,69 @@ static int relabel_by_degree(Tensor* t, int n, int nnz, const int32_t* rowptr, i
   *keycol = col2;
   return SYSTEC_OK;
 }
+
+namespace {
+
+// The column segments (Tensor::nsegs and the seg_* arrays) of a matrix whose
+// panels are built, and the per-call buffer of their sums.
+int build_column_segments(Tensor* t, hipStream_t s) {
+  const int64_t ppos = t->padded;
+  const int n = static_cast<int>(t->dim);
+  const int64_t ntiles = ppos / kPanelTile;
+  Scratch sc;
+  uint32_t *flag = nullptr, *first = nullptr, *count = nullptr, *ptr = nullptr;
+  int rc = sc.alloc(&flag, ppos);
+  if (!rc) rc = sc.alloc(&first, ppos);
+  if (!rc) rc = sc.alloc(&count, n + 1);
+  if (!rc) rc = sc.alloc(&ptr, n + 1);
+  if (rc) return rc;
+  const int grid = static_cast<int>(std::min<int64_t>((ppos + 255) / 256, 65536));
+  seg_flag_kernel<<<grid, 256, 0, s>>>(ppos, t->pcol, flag);
+  if ((rc = check_launch("segment flag kernel"))) return rc;
+  if ((rc = exclusive_sum(flag, first, static_cast<int>(ppos), s))) return rc;
+  uint32_t last_first = 0, last_flag = 0;
+  rc = check_hip(hipMemcpyAsync(&last_first, first + ppos - 1, 4, hipMemcpyDeviceToHost, s), "memcpy");
+  if (!rc)
+    rc = check_hip(hipMemcpyAsync(&last_flag, flag + ppos - 1, 4, hipMemcpyDeviceToHost, s), "memcpy");
+  if (!rc) rc = check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+  if (rc) return rc;
+  const int64_t S = static_cast<int64_t>(last_first) + last_flag;
+  t->nsegs = S;
+  uint32_t *seg_col = nullptr, *seg_col_sorted = nullptr, *ids_in = nullptr;
+  if ((rc = sc.alloc(&seg_col, S)) || (rc = sc.alloc(&seg_col_sorted, S)) ||
+      (rc = sc.alloc(&ids_in, S)))
+    return rc;
+  if ((rc = tensor_alloc(t, &t->seg_tile0, ntiles + 1))) return rc;
+  if ((rc = tensor_alloc(t, &t->seg_colptr, n + 1))) return rc;
+  if ((rc = tensor_alloc(t, &t->seg_ids, S))) return rc;
+  if ((rc = tensor_alloc(t, &t->work_seg, S))) return rc;
+  rc = check_hip(hipMemsetAsync(count, 0, (n + 1) * sizeof(uint32_t), s), "hipMemsetAsync");
+  if (rc) return rc;
+  seg_fill_kernel<<<grid, 256, 0, s>>>(ppos, t->pcol, flag, first, seg_col, t->seg_tile0, count);
+  if ((rc = check_launch("segment fill kernel"))) return rc;
+  const int32_t s32 = static_cast<int32_t>(S);
+  rc = check_hip(hipMemcpyAsync(t->seg_tile0 + ntiles, &s32, 4, hipMemcpyHostToDevice, s), "memcpy");
+  // column pointer: exclusive sum of the counts (n + 1 of them, the last 0)
+  if (!rc) rc = exclusive_sum(count, ptr, n + 1, s);
+  if (!rc)
+    rc = check_hip(hipMemcpyAsync(t->seg_colptr, ptr, (n + 1) * sizeof(int32_t),
+                                  hipMemcpyDeviceToDevice, s), "memcpy");
+  // segment ids grouped by column, in segment order within a column (the
+  // sort is stable)
+  if (!rc) {
+    iota_kernel<<<static_cast<int>(std::min<int64_t>((S + 255) / 256, 65536)), 256, 0, s>>>(
+        S, ids_in);
+    rc = check_launch("iota kernel");
+  }
+  if (!rc)
+    rc = radix_sort_pairs(seg_col, seg_col_sorted, ids_in,
+                          reinterpret_cast<uint32_t*>(t->seg_ids), static_cast<int>(S),
+                          bits_for(n + 1), s);
+  if (!rc) rc = check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+  return rc;
+}
+
+}  // namespace
 
 int tensor_create_csr(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col,
                       const float* val, int panel_rows, int relabel, hipStream_t s,
@@ -435,6 +543,7 @@ int tensor_create_csr(int64_t n, int64_t nnz, const int32_t* rowptr, const int32
                                                       t->pval);
     rc = check_launch("panel pad kernel");
   }
+  if (!rc && ppos > 0) rc = build_column_segments(t, s);
   // the calls' work buffers (see Tensor)
   if (!rc) rc = tensor_alloc(t, &t->work_partial, std::max(1, t->nchunks));
   if (!rc && t->relabeled) {
