@@ -23,7 +23,7 @@ BUILD_DIR = os.path.join(ROOT, "_build", "systec")
 
 SOURCES = ["abi.cpp", "ssymv.hip", "bellman.hip", "mttkrp.hip", "mttkrp_lds.hip", "aux.hip",
            "plan.hip", "serve.cpp", "serve_kernel.hip", "cp.hip", "ttm.hip",
-           "mttkrp_partial.hip", "mttkrp_lane.hip"]
+           "mttkrp_partial.hip", "mttkrp_lane.hip", "ssymv_bucket.hip"]
 
 ARCH = "gfx950"
 COMMON_FLAGS = [

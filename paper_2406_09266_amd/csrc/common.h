@@ -270,6 +270,13 @@ int launch_mttkrp_views_lane(const Tensor* t, const void* B, systec_dtype bdt, i
 // Builds the packed views (Tensor::lview) of a tensor whose views exist, if
 // the one-lane-per-entry form can apply to it; else leaves them empty.
 int build_lane_views(Tensor* t, hipStream_t s);
+// One-shot SSYMV with the column side binned by column range
+// (ssymv_bucket.hip) for matrices of at least kBucketNnzMin stored entries
+// and at most 2^26 rows; -1 (nothing launched) otherwise. y must be zeroed.
+constexpr int64_t kBucketNnzMin = int64_t(1) << 18;
+int launch_ssymv_bucketed(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col,
+                          const float* val, const void* x, systec_dtype xdt, float* y,
+                          hipStream_t s);
 // Whether the one-lane-per-entry form applies to this shape (B fits one
 // workgroup's LDS, R is 8 in BF16, 16 or 32); the tensor's runs decide the
 // rest.

@@ -43,6 +43,7 @@ struct LaneEntries {
   int col[kV];
   float val[kV];
   int valid;  // number of valid entries of this lane (0..8)
+  int count;  // entries of the tile (wave-uniform)
 };
 
 // Per-wave LDS staging: row-start markers and the tile's columns and values.
@@ -55,6 +56,12 @@ struct TileLds {
 // Loads merge-path tile `tile` (items [tile*kTile, (tile+1)*kTile) of the
 // n + nnz sequence): at most kTile rows and kTile entries. Returns false if
 // the tile holds no entry.
+__device__ __forceinline__ bool load_tile_split(const int32_t* __restrict__ rowptr,
+                                                const int32_t* __restrict__ col,
+                                                const float* __restrict__ val, int n, int nnz,
+                                                int64_t tile, int i0, int i1, int lane,
+                                                TileLds& S, LaneEntries& L);
+
 __device__ __forceinline__ bool load_tile(const int32_t* __restrict__ rowptr,
                                           const int32_t* __restrict__ col,
                                           const float* __restrict__ val, int n, int nnz,
@@ -62,8 +69,20 @@ __device__ __forceinline__ bool load_tile(const int32_t* __restrict__ rowptr,
   const int64_t total = static_cast<int64_t>(n) + nnz;
   const int64_t d0 = tile * kTile;
   const int64_t d1 = min(d0 + kTile, total);
-  const int i0 = merge_split(rowptr, n, d0, lane);
-  const int i1 = merge_split(rowptr, n, d1, lane);
+  return load_tile_split(rowptr, col, val, n, nnz, tile, merge_split(rowptr, n, d0, lane),
+                         merge_split(rowptr, n, d1, lane), lane, S, L);
+}
+
+// load_tile with the tile's merge-path split rows given: i0 = the split of
+// diagonal tile * kTile, i1 = that of the tile's end.
+__device__ __forceinline__ bool load_tile_split(const int32_t* __restrict__ rowptr,
+                                                const int32_t* __restrict__ col,
+                                                const float* __restrict__ val, int n, int nnz,
+                                                int64_t tile, int i0, int i1, int lane,
+                                                TileLds& S, LaneEntries& L) {
+  const int64_t total = static_cast<int64_t>(n) + nnz;
+  const int64_t d0 = tile * kTile;
+  const int64_t d1 = min(d0 + kTile, total);
   const int j0 = static_cast<int>(d0 - i0);
   const int j1 = static_cast<int>(d1 - i1);
   const int cnt = j1 - j0;  // 0..kTile
@@ -107,6 +126,7 @@ __device__ __forceinline__ bool load_tile(const int32_t* __restrict__ rowptr,
   for (int k = 0; k < kV; ++k) L.row[k] = max(h[k], carry);
 
   L.valid = max(0, min(kV, cnt - lane * kV));
+  L.count = cnt;
   int c[kV];
   read8(S.col + lane * kV, c);
   const float* vp = S.val + lane * kV;

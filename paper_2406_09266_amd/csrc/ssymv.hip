@@ -270,6 +270,10 @@ int launch_ssymv(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* c
                  hipStream_t s) {
   int rc = launch_fill_f32(y, n, s);
   if (rc != SYSTEC_OK || nnz == 0) return rc;
+  if (symmetric) {
+    rc = launch_ssymv_bucketed(n, nnz, rowptr, col, val, x, xdt, y, s);
+    if (rc != -1) return rc;
+  }
   const int ni = static_cast<int>(n), nz = static_cast<int>(nnz);
   if (xdt == SYSTEC_F32) {
     const float* xf = static_cast<const float*>(x);

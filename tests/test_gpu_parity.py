@@ -83,6 +83,42 @@ def test_ssymv_matches_oracle(case, xdtype):
         assert rel_err(y, full) <= TOL_BF16_E2E
 
 
+# matrices of at least 2^18 stored entries, where the one-shot SSYMV bins
+# the column side by ranges of 16,384 columns (several buckets, a ragged
+# last bucket, hub rows, rows without entries)
+SSYMV_BUCKETED_CASES = {
+    "rmat_scale18": lambda: synth.ssymv_rmat(scale=18, batch=1 << 21, seed=31),
+    "uniform_n70001": lambda: synth.ssymv_uniform(70001, 9, seed=32),
+    "random_degree_n150000": lambda: synth.ssymv_random_degree(150000, 6, seed=33),
+}
+
+
+@pytest.mark.parametrize("case", sorted(SSYMV_BUCKETED_CASES))
+@pytest.mark.parametrize("xdtype", ["f32", "bf16"])
+def test_ssymv_bucketed_matches_oracle(case, xdtype):
+    m = SSYMV_BUCKETED_CASES[case]()
+    assert m["col"].size >= 1 << 18
+    print(f"ssymv bucketed case={case} x={xdtype} n={m['n']} nnz={m['col'].size}", flush=True)
+    y, want, _ = _ssymv_case(m, xdtype)
+    x_ref = f32(m["x"]) if xdtype == "f32" else _bf16_round(m["x"])
+    scale, _ = oracle.ssymv(m["n"], m["rowptr"], m["col"], np.abs(f32(m["val"])), np.abs(x_ref))
+    assert_elementwise(y, want, scale, TOL32, f"ssymv bucketed {case}")
+    assert rel_err(y, want) <= TOL32
+
+
+def test_ssymv_bucketed_one_long_row():
+    # row 0 holds every column of a 300,000-column matrix: one row across
+    # every bucket, every other row empty
+    n = 300000
+    rowptr = np.full(n + 1, n, dtype=np.int32)
+    rowptr[0] = 0
+    m = {"n": n, "rowptr": rowptr, "col": np.arange(n, dtype=np.int32),
+         "val": synth.dense_uniform(n, seed=5), "x": synth.dense_uniform(n, seed=6)}
+    y, want, _ = _ssymv_case(m)
+    scale, _ = oracle.ssymv(n, m["rowptr"], m["col"], np.abs(f32(m["val"])), np.abs(f32(m["x"])))
+    assert_elementwise(y, want, scale, TOL32, "ssymv bucketed long row")
+
+
 def test_ssymv_empty_and_single():
     import torch
     n = 37
