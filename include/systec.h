@@ -85,7 +85,12 @@ SYSTEC_API const char* systec_version(void);
  * figure). The stored value of a diagonal entry is not pre-scaled.
  *   x       device, n elements of dtype xdt (F32 or BF16)
  *   y       device float[n], overwritten.
- * n >= 1, 0 <= nnz < 2^31. Errors: EINVAL, EDEVICE.
+ * n >= 1, 0 <= nnz < 2^31. Errors: EINVAL, EDEVICE, ENOMEM.
+ * From 2^18 stored entries (and up to 2^26 rows) the column-side updates
+ * are binned by ranges of 16,384 columns and summed in LDS instead of sent
+ * as device atomics; the call then allocates stream-ordered scratch
+ * (hipMallocAsync, about 8 bytes per stored entry), freed on the stream
+ * when the call's work is done.
  * ---------------------------------------------------------------------- */
 SYSTEC_API int systec_ssymv(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col,
                  const float* val, const void* x, systec_dtype xdt, float* y,

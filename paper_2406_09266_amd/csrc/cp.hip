@@ -256,7 +256,10 @@ int launch_cp_step(const Tensor* t, const void* B, systec_dtype bdt, int64_t R, 
   const int I = static_cast<int>(t->dim);
   const int Ri = static_cast<int>(R);
   const int RR = Ri * Ri;
-  int rc = launch_mttkrp_views(t, B, bdt, R, C, s);
+  // the MTTKRP as the automatic choice runs it: the one-lane-per-entry form
+  // with B in LDS where it applies, else the slot views
+  int rc = mttkrp_lane_shape_fits(I, bdt, R) ? launch_mttkrp_views_lane(t, B, bdt, R, C, s) : -1;
+  if (rc == -1) rc = launch_mttkrp_views(t, B, bdt, R, C, s);
   if (rc) return rc;
   // workspace: Gram partials, H^-1, the inner-product and norm partials and
   // ||[[B]]||^2 (one double), stream-ordered

@@ -274,9 +274,10 @@ int bucketed(int n, int nnz, const int32_t* rowptr, const int32_t* col, const fl
   const size_t b_split = up(static_cast<size_t>(tiles + 1) * 4);
   const size_t bytes = 2 * b_count + b_items + b_n + b_scan + b_bin + b_split;
   unsigned char* scratch = nullptr;
-  rc = check_hip(hipMallocAsync(reinterpret_cast<void**>(&scratch), bytes, s),
-                 "hipMallocAsync(ssymv bucket scratch)");
-  if (rc) return rc;
+  const hipError_t ae = hipMallocAsync(reinterpret_cast<void**>(&scratch), bytes, s);
+  if (ae != hipSuccess)
+    return fail(SYSTEC_ENOMEM, std::string("hipMallocAsync(ssymv bucket scratch): ") +
+                                   hipGetErrorString(ae));
   auto* count = reinterpret_cast<uint32_t*>(scratch);
   auto* offset = reinterpret_cast<uint32_t*>(scratch + b_count);
   auto* items = reinterpret_cast<int4*>(scratch + 2 * b_count);
