@@ -164,10 +164,14 @@ struct Tensor {
   // Packed views for the one-lane-per-entry MTTKRP with B in LDS, built
   // when that form can apply (I * 16 bytes fits one workgroup's LDS, so I <
   // 65,536, and the runs are long): view t as records of lane_words 32-bit
-  // words, ceil(N/2) words of two 16-bit indices (slot 2q in the low half)
-  // and then coef[mask][t] * v in FP32; each view padded to a multiple of 64
-  // records of weight 0 whose output index is the view's last one.
+  // words, the N - 1 indices other than slot t as 16-bit halves (two to a
+  // word, in slot order) and then coef[mask][t] * v in FP32, grouped by the
+  // output index c_t through a row pointer (the leading-index level of a
+  // compressed fiber layout); each view padded to a multiple of 64 records
+  // of weight 0 that belong to its last output row.
   uint32_t* lview[5] = {};
+  int32_t* lrowptr[5] = {};    // per view: first record of each output row (I + 1)
+  int32_t* ltile_row[5] = {};  // per view: output row of each 512-record tile's first record
   int64_t lnnz[5] = {0, 0, 0, 0, 0};  // padded record counts
   int lane_words = 0;
   // serving (built at registration)

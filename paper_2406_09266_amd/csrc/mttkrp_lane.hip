@@ -11,18 +11,22 @@
 // C[c_t, :], the sum over a run of equal c_t kept in registers (Sec. 4.2.8).
 //
 // Why this layout. Lane l of a wave takes record base + l, so one load of
-// 12 or 16 bytes per lane brings the wave 64 whole records (the N indices as
-// 16-bit halves and the weight coef * v, computed once when the tensor is
-// prepared), and the loads of the next kDepth iterations are in flight while
-// one is consumed; the N - 1 factor rows of the record are read from LDS. The
-// lane keeps the R partial sums of the wave's current output row. When the
-// row changes inside an iteration, the lanes' sums are added across the wave
-// by a transposing butterfly (each exchange halves the columns a lane holds,
-// so R = 16 columns take 15 exchanges instead of 16 full reductions), and
-// rows that begin and end inside one iteration are summed by a segmented
-// scan across the lanes. The views are padded to whole iterations with
-// records of weight 0 on the view's last row, so the loop has no bounds
-// checks.
+// 8 or 12 bytes per lane brings the wave 64 whole records (the N - 1 indices
+// other than the output's as 16-bit halves and the weight coef * v,
+// computed once when the tensor is prepared; the output index is not
+// stored: each view's records are grouped by it through a row pointer, the
+// leading-index level of a compressed fiber layout, Sec. 2.2), and the loads
+// of the next kDepth iterations are in flight while one is consumed; the
+// N - 1 factor rows of the record are read from LDS. The lane keeps the R
+// partial sums of the wave's current output row; an iteration that stays
+// in that row (known from the row pointer) just accumulates. When the row
+// changes inside an iteration, each lane finds its record's row from the
+// row pointer, the lanes' sums are added across the wave by a transposing
+// butterfly (each exchange halves the columns a lane holds, so R = 16
+// columns take 15 exchanges instead of 16 full reductions), and rows that
+// begin and end inside one iteration are summed by a segmented scan across
+// the lanes. The views are padded to whole iterations with records of
+// weight 0 on the view's last row, so the loop has no bounds checks.
 #include "common.h"
 #include "mttkrp_device.h"
 #include "wave_ops.h"
@@ -39,7 +43,9 @@ constexpr int kLaneTile = 512;  // records per wave tile (a multiple of 64)
 // take most of the registers)
 constexpr int depth_of(int R) { return R >= 32 ? 2 : 4; }
 
-constexpr int lane_words_of(int N) { return (N + 1) / 2 + 1; }
+// record words: the N - 1 indices other than the view's slot, two 16-bit
+// halves to a word, then the weight
+constexpr int lane_words_of(int N) { return N / 2 + 1; }
 
 // LDS after the factor: the workgroup's tile counter and the flag of an
 // inexact FP16 conversion (the kernel declares no static LDS, so B starts
@@ -48,6 +54,8 @@ constexpr int kLaneExtraLds = 16;
 
 struct LaneViews {
   const uint32_t* rec[5];
+  const int32_t* rowptr[5];    // per view: first record of each output row (I + 1)
+  const int32_t* tile_row[5];  // per view: output row of each tile's first record
   int nrec[5];   // padded record counts (multiples of 64)
   int tile0[6];  // first tile of each view; tile0[N] = total
 };
@@ -65,9 +73,67 @@ __device__ __forceinline__ void load_record(const uint32_t* __restrict__ rec, in
   }
 }
 
-template <int S, int K>
-__device__ __forceinline__ int index_of(const uint32_t (&w)[K]) {
-  return (S & 1) ? static_cast<int>(w[S / 2] >> 16) : static_cast<int>(w[S / 2] & 0xffffu);
+// A window of a view's row pointer: lane j holds rowptr[wbase + j] (INT_MAX
+// past row I), the starts of rows wbase .. wbase + 63.
+struct RowWindow {
+  int wbase;
+  int start;
+};
+
+__device__ __forceinline__ RowWindow load_row_window(const int32_t* __restrict__ rowptr, int I,
+                                                     int wbase, int lane) {
+  const int r = wbase + lane;
+  return RowWindow{wbase, r <= I ? rowptr[r] : INT_MAX};
+}
+
+// The output row of record e, for each lane of the wave, given that the
+// wave's records lie in rows cur and above (rows up to cur start at or before
+// e - lane): cur plus the starts of rows above cur at or below e. The starts come from the window when it
+// covers them (it is reloaded from row cur + 1 otherwise); with few starts
+// inside the wave's records (long rows) each is compared directly, else each
+// lane binary-searches the 64 starts held across the lanes.
+__device__ __forceinline__ int lane_row(const int32_t* __restrict__ rowptr, int I, int cur, int e,
+                                        int lane, RowWindow& win) {
+  const int e_max = __builtin_amdgcn_readlane(e, kWave - 1);
+  int off = cur + 1 - win.wbase;  // window lanes below off hold rows up to cur
+  if (off < 0 || off >= kWave) {
+    win = load_row_window(rowptr, I, cur + 1, lane);
+    off = 0;
+  }
+  // rows wbase .. cur start at or before every lane's record and are counted
+  // below with the rest; they are not above cur
+  int count = -off;
+  for (;;) {  // wave-uniform
+    const int b = win.start;
+    uint64_t reach = __ballot(b <= e_max);  // the starts inside the wave's records
+    const int b_last = __builtin_amdgcn_readlane(b, kWave - 1);
+    if (__popcll(reach) <= 4) {
+      while (reach) {
+        const int j = __ffsll(static_cast<long long>(reach)) - 1;
+        count += e >= __builtin_amdgcn_readlane(b, j) ? 1 : 0;
+        reach &= reach - 1;
+      }
+    } else {
+      int pos = 0;  // starts b_0 .. b_{pos-1} are <= e (b ascends across lanes)
+#pragma unroll
+      for (int k = kWave / 2; k >= 1; k /= 2)
+        if (__shfl(b, pos + k - 1) <= e) pos += k;
+      if (pos == kWave - 1 && b_last <= e) pos = kWave;
+      count += pos;
+    }
+    if (b_last > e_max) break;  // no later start is at or below any lane's record
+    win = load_row_window(rowptr, I, win.wbase + kWave, lane);
+  }
+  return cur + count;
+}
+
+// The start of row cur + 1 (the first record past row cur), from the window
+// when it holds it.
+__device__ __forceinline__ int next_row_start(const int32_t* __restrict__ rowptr, int I, int cur,
+                                              int lane, RowWindow& win) {
+  const int j = cur + 1 - win.wbase;
+  if (j < 0 || j >= kWave) win = load_row_window(rowptr, I, cur + 1, lane);
+  return __builtin_amdgcn_readlane(win.start, cur + 1 - win.wbase);
 }
 
 template <typename BT, int R>
@@ -238,9 +304,8 @@ template <int N, typename BT, int R, int T, int K>
 __device__ __forceinline__ void lds_rows(const uint32_t (&w)[K], const BT* sB, int plane,
                                          uint4 (&raw)[N - 1][pieces_of<BT, R>()]) {
 #pragma unroll
-  for (int r = 0; r < N - 1; ++r) {
-    const int s = r < T ? r : r + 1;  // the slots other than T, in order
-    const int c = (s & 1) ? static_cast<int>(w[s / 2] >> 16) : static_cast<int>(w[s / 2] & 0xffffu);
+  for (int r = 0; r < N - 1; ++r) {  // record position r holds the r-th slot other than T
+    const int c = (r & 1) ? static_cast<int>(w[r / 2] >> 16) : static_cast<int>(w[r / 2] & 0xffffu);
     lds_row_raw<BT, R>(sB, plane, c, raw[r]);
   }
 }
@@ -251,14 +316,18 @@ __device__ __forceinline__ void lds_rows(const uint32_t (&w)[K], const BT* sB, i
 // and every product is one mixed-precision FMA: kv * b_1, times b_2, ...,
 // the last row fused with the accumulation (4 operations per column for
 // N = 5, against 8 with BF16 rows widened to FP32 first).
+// The wave's iteration covers records [it, it + 64); `bound` is the first
+// record of row cur + 1, so the iteration stays in row cur when it + 64 <=
+// bound (the rows' starts come from the view's row pointer, not from the
+// records).
 template <int N, typename BT, int R, int T, int K, bool kHalf>
 __device__ __forceinline__ void lane_step(const uint32_t (&w)[K], float (&acc)[R], int& cur,
-                                          int lane, const BT* sB, int plane,
-                                          float* __restrict__ C) {
+                                          int& bound, RowWindow& win, int it,
+                                          const int32_t* __restrict__ rowptr, int I, int lane,
+                                          const BT* sB, int plane, float* __restrict__ C) {
   constexpr int kP = pieces_of<BT, R>();
   const float kv = __uint_as_float(w[K - 1]);
-  const int row = index_of<T, K>(w);
-  const int last = __builtin_amdgcn_readlane(row, kWave - 1);
+  const bool whole = it + kWave <= bound;  // wave-uniform
   float p[R];  // the lane's product coef * v * prod_{s != T} B[c_s, :]
   if constexpr (kHalf) {
     static_assert(sizeof(BT) == 2 && (N - 1) * kP <= 8, "FP16 rows in registers");
@@ -278,7 +347,7 @@ __device__ __forceinline__ void lane_step(const uint32_t (&w)[K], float (&acc)[R
     for (int q = 0; q < kP; ++q)
       asm volatile("" ::"v"(raw[N - 2][q].x), "v"(raw[N - 2][q].y), "v"(raw[N - 2][q].z),
                    "v"(raw[N - 2][q].w));
-    if (last == cur) {  // the whole iteration continues the current row
+    if (whole) {  // the whole iteration continues the current row
 #pragma unroll
       for (int j = 0; j < R; ++j) acc[j] = fmaf(p[j], half_at<R>(raw[N - 2], j), acc[j]);
       return;
@@ -305,7 +374,8 @@ __device__ __forceinline__ void lane_step(const uint32_t (&w)[K], float (&acc)[R
 #pragma unroll
       for (int s = 0; s < N; ++s) {
         if (s == T) continue;
-        const int c = (s & 1) ? static_cast<int>(w[s / 2] >> 16) : static_cast<int>(w[s / 2] & 0xffffu);
+        const int q = s < T ? s : s - 1;  // its record position
+        const int c = (q & 1) ? static_cast<int>(w[q / 2] >> 16) : static_cast<int>(w[q / 2] & 0xffffu);
         uint4 raw[kP];
         lds_row_raw<BT, R>(sB, plane, c, raw);
         float b[R];
@@ -315,7 +385,7 @@ __device__ __forceinline__ void lane_step(const uint32_t (&w)[K], float (&acc)[R
         first = false;
       }
     }
-    if (last == cur) {  // the weight applied last, fused with the accumulation
+    if (whole) {  // the weight applied last, fused with the accumulation
 #pragma unroll
       for (int j = 0; j < R; ++j) acc[j] = fmaf(p[j], kv, acc[j]);
       return;
@@ -324,6 +394,8 @@ __device__ __forceinline__ void lane_step(const uint32_t (&w)[K], float (&acc)[R
     for (int j = 0; j < R; ++j) p[j] *= kv;
   }
   // the row changes inside this iteration
+  const int row = lane_row(rowptr, I, cur, it + lane, lane, win);
+  const int last = __builtin_amdgcn_readlane(row, kWave - 1);
 #pragma unroll
   for (int j = 0; j < R; ++j) acc[j] += (row == cur) ? p[j] : 0.0f;
   flush_row<R>(C, cur, acc, lane);
@@ -341,6 +413,7 @@ __device__ __forceinline__ void lane_step(const uint32_t (&w)[K], float (&acc)[R
 #pragma unroll
   for (int j = 0; j < R; ++j) acc[j] = (row == last) ? p[j] : 0.0f;
   cur = last;
+  bound = next_row_start(rowptr, I, cur, lane, win);
 }
 
 // A wave runs records [e0, e1) of view T (wave-uniform, both multiples of
@@ -348,7 +421,9 @@ __device__ __forceinline__ void lane_step(const uint32_t (&w)[K], float (&acc)[R
 // of registers; near the end of the range they re-read its last iteration
 // (in bounds, never consumed), so that no load sits under a branch.
 template <int N, typename BT, int R, int T, bool kHalf>
-__device__ __forceinline__ void lane_view_range(int e0, int e1, const uint32_t* __restrict__ rec,
+__device__ __forceinline__ void lane_view_range(int e0, int e1, int row0,
+                                                const uint32_t* __restrict__ rec,
+                                                const int32_t* __restrict__ rowptr, int I,
                                                 const BT* sB, int plane, float* __restrict__ C) {
   constexpr int K = lane_words_of(N);
   constexpr int kDepth = depth_of(R);
@@ -357,7 +432,9 @@ __device__ __forceinline__ void lane_view_range(int e0, int e1, const uint32_t* 
   uint32_t ring[kDepth][K];
 #pragma unroll
   for (int d = 0; d < kDepth; ++d) load_record<K>(rec, min(e0 + d * kWave, e_last) + lane, ring[d]);
-  int cur = __builtin_amdgcn_readfirstlane(index_of<T, K>(ring[0]));
+  int cur = row0;  // the row of record e0
+  RowWindow win = load_row_window(rowptr, I, cur + 1, lane);  // the starts of the next rows
+  int bound = __builtin_amdgcn_readlane(win.start, 0);
   float acc[R];
 #pragma unroll
   for (int j = 0; j < R; ++j) acc[j] = 0.0f;
@@ -370,28 +447,33 @@ __device__ __forceinline__ void lane_view_range(int e0, int e1, const uint32_t* 
 #pragma unroll
       for (int q = 0; q < K; ++q) w[q] = ring[d][q];
       load_record<K>(rec, min(it + (kDepth + d) * kWave, e_last) + lane, ring[d]);
-      lane_step<N, BT, R, T, K, kHalf>(w, acc, cur, lane, sB, plane, C);
+      lane_step<N, BT, R, T, K, kHalf>(w, acc, cur, bound, win, it + d * kWave, rowptr, I, lane,
+                                       sB, plane, C);
     }
   }
   // the last iterations (fewer than kDepth), already in the ring
 #pragma unroll
   for (int d = 0; d + 1 < kDepth; ++d)
-    if (it + d * kWave < e1) lane_step<N, BT, R, T, K, kHalf>(ring[d], acc, cur, lane, sB, plane, C);
+    if (it + d * kWave < e1)
+      lane_step<N, BT, R, T, K, kHalf>(ring[d], acc, cur, bound, win, it + d * kWave, rowptr, I,
+                                       lane, sB, plane, C);
   flush_row<R>(C, cur, acc, lane);
 }
 
 template <int N, typename BT, int R, bool kHalf>
-__device__ __forceinline__ void lane_view_slot(int t, int e0, int e1, const LaneViews& vs,
-                                               const BT* sB, int plane, float* C) {
+__device__ __forceinline__ void lane_view_slot(int t, int e0, int e1, int row0, const LaneViews& vs,
+                                               int I, const BT* sB, int plane, float* C) {
   switch (t) {
-    case 0: lane_view_range<N, BT, R, 0, kHalf>(e0, e1, vs.rec[0], sB, plane, C); break;
-    case 1: lane_view_range<N, BT, R, 1, kHalf>(e0, e1, vs.rec[1], sB, plane, C); break;
-    case 2: lane_view_range<N, BT, R, 2, kHalf>(e0, e1, vs.rec[2], sB, plane, C); break;
+    case 0: lane_view_range<N, BT, R, 0, kHalf>(e0, e1, row0, vs.rec[0], vs.rowptr[0], I, sB, plane, C); break;
+    case 1: lane_view_range<N, BT, R, 1, kHalf>(e0, e1, row0, vs.rec[1], vs.rowptr[1], I, sB, plane, C); break;
+    case 2: lane_view_range<N, BT, R, 2, kHalf>(e0, e1, row0, vs.rec[2], vs.rowptr[2], I, sB, plane, C); break;
     case 3:
-      if constexpr (N > 3) lane_view_range<N, BT, R, 3, kHalf>(e0, e1, vs.rec[3], sB, plane, C);
+      if constexpr (N > 3)
+        lane_view_range<N, BT, R, 3, kHalf>(e0, e1, row0, vs.rec[3], vs.rowptr[3], I, sB, plane, C);
       break;
     default:
-      if constexpr (N > 4) lane_view_range<N, BT, R, 4, kHalf>(e0, e1, vs.rec[4], sB, plane, C);
+      if constexpr (N > 4)
+        lane_view_range<N, BT, R, 4, kHalf>(e0, e1, row0, vs.rec[4], vs.rowptr[4], I, sB, plane, C);
       break;
   }
 }
@@ -403,8 +485,8 @@ __device__ __forceinline__ void lane_view_slot(int t, int e0, int e1, const Lane
 // workgroup ends with its last tile, not with its slowest wave. `next` holds
 // kLaneWaves (the first tiles go to the waves in order) when this begins.
 template <int N, typename BT, int R, bool kHalf>
-__device__ __forceinline__ void lane_tiles(const LaneViews& vs, const BT* sB, int plane, float* C,
-                                           int* next) {
+__device__ __forceinline__ void lane_tiles(const LaneViews& vs, int I, const BT* sB, int plane,
+                                           float* C, int* next) {
   const int lane = threadIdx.x & (kWave - 1);
   int k = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   for (;;) {
@@ -417,9 +499,11 @@ __device__ __forceinline__ void lane_tiles(const LaneViews& vs, const BT* sB, in
     for (int q = 1; q < N; ++q) t += (tile >= vs.tile0[q]) ? 1 : 0;
     // wave-uniform: scalar registers and branches
     t = __builtin_amdgcn_readfirstlane(t);
-    const int e0 = __builtin_amdgcn_readfirstlane((tile - vs.tile0[t]) * kLaneTile);
+    const int local = tile - vs.tile0[t];
+    const int e0 = __builtin_amdgcn_readfirstlane(local * kLaneTile);
     const int e1 = __builtin_amdgcn_readfirstlane(min(vs.nrec[t], e0 + kLaneTile));
-    lane_view_slot<N, BT, R, kHalf>(t, e0, e1, vs, sB, plane, C);
+    const int row0 = __builtin_amdgcn_readfirstlane(vs.tile_row[t][local]);
+    lane_view_slot<N, BT, R, kHalf>(t, e0, e1, row0, vs, I, sB, plane, C);
     k = __builtin_amdgcn_readfirstlane(claim);
   }
 }
@@ -454,13 +538,13 @@ __global__ __launch_bounds__(kLaneThreads) void mttkrp_views_lane_kernel(LaneVie
     if (inexact) atomicOr(inexact_flag, 1);
     __syncthreads();
     if (*inexact_flag == 0) {
-      lane_tiles<N, BT, R, true>(vs, sB, plane, C, next);
+      lane_tiles<N, BT, R, true>(vs, I, sB, plane, C, next);
       return;
     }
   }
   for (int q = threadIdx.x; q < pieces; q += kLaneThreads) dst[(q % kP) * I + q / kP] = src[q];
   __syncthreads();
-  lane_tiles<N, BT, R, false>(vs, sB, plane, C, next);
+  lane_tiles<N, BT, R, false>(vs, I, sB, plane, C, next);
 }
 
 template <int N, typename BT, int R>
@@ -469,6 +553,8 @@ int launch_lane(const Tensor* tn, const BT* B, float* C, size_t lds, int cus, hi
   int tiles = 0;
   for (int t = 0; t < N; ++t) {
     vs.rec[t] = tn->lview[t];
+    vs.rowptr[t] = tn->lrowptr[t];
+    vs.tile_row[t] = tn->ltile_row[t];
     vs.nrec[t] = static_cast<int>(tn->lnnz[t]);
     vs.tile0[t] = tiles;
     tiles += static_cast<int>((tn->lnnz[t] + kLaneTile - 1) / kLaneTile);
@@ -509,7 +595,9 @@ int launch_lane_r(const Tensor* tn, const BT* B, int R, float* C, size_t lds, in
 
 // Record e of packed view T from the view's entry e (weight coef * v, the
 // product the kernels over the unpacked views form), or a padding record of
-// weight 0 on the view's last output row.
+// weight 0 (it belongs to the view's last output row). The record holds
+// the indices of the slots other than T; the output row is the view's
+// row pointer's business.
 template <int N, int T>
 __global__ void lane_pack_kernel(IdxPtrs ip, const float* __restrict__ val, int m, int padded,
                                  uint32_t* __restrict__ out) {
@@ -525,16 +613,35 @@ __global__ void lane_pack_kernel(IdxPtrs ip, const float* __restrict__ val, int 
   } else {
 #pragma unroll
     for (int q = 0; q < N; ++q) c[q] = 0;
-    c[T] = ip.p[T][m - 1];
   }
-  uint32_t* o = out + static_cast<int64_t>(e) * K;
+  int o[N - 1];
+#pragma unroll
+  for (int s = 0, r = 0; s < N; ++s)
+    if (s != T) o[r++] = c[s];
+  uint32_t* dst = out + static_cast<int64_t>(e) * K;
 #pragma unroll
   for (int q = 0; q + 1 < K; ++q) {
-    const uint32_t lo = static_cast<uint32_t>(c[2 * q]);
-    const uint32_t hi = 2 * q + 1 < N ? static_cast<uint32_t>(c[2 * q + 1]) : 0u;
-    o[q] = lo | (hi << 16);
+    const uint32_t lo = static_cast<uint32_t>(o[2 * q]);
+    const uint32_t hi = 2 * q + 1 < N - 1 ? static_cast<uint32_t>(o[2 * q + 1]) : 0u;
+    dst[q] = lo | (hi << 16);
   }
-  o[K - 1] = __float_as_uint(kv);
+  dst[K - 1] = __float_as_uint(kv);
+}
+
+// The row pointer of a packed view: rowptr[r] = the first record whose row
+// is r or more (records [m, padded) belong to the last row), for r in [0, I];
+// and the row of each tile's first record.
+__global__ void lane_rowptr_kernel(const int32_t* __restrict__ rows, int m, int padded, int I,
+                                   int32_t* __restrict__ rowptr, int32_t* __restrict__ tile_row) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= padded) return;
+  const int last_row = rows[m - 1];
+  const int row = e < m ? rows[e] : last_row;
+  const int prev = e == 0 ? -1 : (e - 1 < m ? rows[e - 1] : last_row);
+  for (int r = prev + 1; r <= row; ++r) rowptr[r] = e;  // rows starting here (empty ones too)
+  if (e == padded - 1)
+    for (int r = row + 1; r <= I; ++r) rowptr[r] = padded;
+  if (e % kLaneTile == 0) tile_row[e / kLaneTile] = row;
 }
 
 template <int N, int T>
@@ -544,7 +651,11 @@ int pack_view(const Tensor* t, uint32_t* out, hipStream_t s) {
   const int m = static_cast<int>(t->vnnz[T]);
   const int padded = static_cast<int>(t->lnnz[T]);
   lane_pack_kernel<N, T><<<(padded + 255) / 256, 256, 0, s>>>(ip, t->vval[T], m, padded, out);
-  return check_launch("mttkrp lane pack kernel");
+  if (const int rc = check_launch("mttkrp lane pack kernel")) return rc;
+  lane_rowptr_kernel<<<(padded + 255) / 256, 256, 0, s>>>(t->vidx[T][T], m, padded,
+                                                          static_cast<int>(t->dim), t->lrowptr[T],
+                                                          t->ltile_row[T]);
+  return check_launch("mttkrp lane row pointer kernel");
 }
 
 template <int N>
@@ -596,6 +707,9 @@ int build_lane_views(Tensor* t, hipStream_t s) {
     t->lnnz[v] = (t->vnnz[v] + kWave - 1) / kWave * kWave;
     if (t->lnnz[v] == 0) continue;
     rc = tensor_alloc(t, &t->lview[v], static_cast<size_t>(t->lnnz[v]) * K);
+    if (!rc) rc = tensor_alloc(t, &t->lrowptr[v], static_cast<size_t>(t->dim) + 1);
+    if (!rc)
+      rc = tensor_alloc(t, &t->ltile_row[v], static_cast<size_t>((t->lnnz[v] + kLaneTile - 1) / kLaneTile));
     if (rc) break;
     rc = N == 3   ? pack_view_slot<3>(t, v, t->lview[v], s)
          : N == 4 ? pack_view_slot<4>(t, v, t->lview[v], s)
