@@ -337,7 +337,7 @@ SYSTEC_API int systec_quantize_bf16(const float* in, uint16_t* out, int64_t n, s
  * segmented reductions (the data rearrangement the paper keeps outside its
  * timings, Sec. 5.2, and the symmetry-aware storage it names as future work,
  * Sec. 7). The canonical entries are kept, only reordered:
- *  - matrix: rows cut into panels of 16384 rows; inside a panel the stored
+ *  - matrix: rows cut into panels of 8192 rows; inside a panel the stored
  *    entries are sorted by (column, row). systec_ssymv_t keeps the panel's
  *    row sums in LDS and reduces the column side by segments.
  *  - tensor of order 3..5: one slot view per index slot t, holding the

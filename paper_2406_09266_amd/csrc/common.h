@@ -322,10 +322,11 @@ struct ZeroArgs {
   float* ptr[kStepReqs];
   int64_t count[kStepReqs];
 };
-// Prepared SSYMV panels: 16,384 rows (64 KiB of FP32 row sums in LDS), run
-// by 1,024-thread workgroups.
-constexpr int kPanelRows = 16384;
-constexpr int kPanelThreads = 1024;
+// Prepared SSYMV panels: 8,192 rows (32 KiB of FP32 row sums in LDS, 48 KiB
+// with the staged BF16 x slice, so three workgroups share a CU), run by
+// 512-thread workgroups.
+constexpr int kPanelRows = 8192;
+constexpr int kPanelThreads = 512;
 constexpr int kServeBlock = kPanelThreads;  // SSYMV step kernel
 constexpr int kServeMttkrpBlock = 256; // MTTKRP step kernel
 constexpr int kServeLds = kPanelRows * 4;  // bytes: the FP32 row sums of one panel

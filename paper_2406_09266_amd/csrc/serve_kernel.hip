@@ -93,8 +93,8 @@ __device__ __forceinline__ void view_range(const ServeTensor* t, const ServeUnit
                                     0, q.R);
 }
 
-// SSYMV items need the panel's row sums in LDS (1,024 threads, 64 KiB, and
-// 32 KiB more for a BF16 request's staged x slice); MTTKRP
+// SSYMV items need the panel's row sums in LDS (512 threads, 32 KiB, and
+// 16 KiB more for a BF16 request's staged x slice); MTTKRP
 // items need no LDS and run at full occupancy (256 threads, one kernel per
 // tensor order so that each keeps the registers of its own order); the four
 // waves of an MTTKRP workgroup share an item of a few tiles each.

@@ -403,7 +403,7 @@ int panel_call(const Tensor* t, const void* x, systec_dtype xdt, float* y, bool 
   if (rc != SYSTEC_OK) return rc;
   if (xdt == SYSTEC_F32) return panel_launch<float, false>(t, static_cast<const float*>(x), y, s);
   // BF16 x: the panel's slice of x goes to LDS beside the row sums when the
-  // device allows that much per workgroup (16384 rows: 96 KiB)
+  // device allows that much per workgroup (8192 rows: 48 KiB)
   int dev = 0;
   int limit = 0;
   rc = check_hip(hipGetDevice(&dev), "hipGetDevice");
