@@ -151,16 +151,28 @@ __global__ __launch_bounds__(kPanelThreads) void ssymv_panel_kernel(
 // matrix the output permutation follows as its own gather: scattering y
 // through the permutation here was slower, 0.252 against 0.248 ms per call
 // at R-MAT scale 22.)
-__global__ void panel_colsum_kernel(int n, const int32_t* __restrict__ colptr,
-                                    const int32_t* __restrict__ seg_ids,
-                                    const float* __restrict__ seg_val, float* __restrict__ y) {
-  const int stride = gridDim.x * blockDim.x;
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += stride) {
-    const int k1 = colptr[c + 1];
-    float v = 0.0f;
-    for (int k = colptr[c]; k < k1; ++k) v += seg_val[seg_ids[k]];
-    if (k1 > colptr[c]) y[c] += v;
+__global__ __launch_bounds__(256) void panel_colsum_kernel(int n, const int32_t* __restrict__ colptr,
+                                                          const int32_t* __restrict__ seg_ids,
+                                                          const float* __restrict__ seg_val,
+                                                          float* __restrict__ y) {
+  // one thread per column; its loads go out in groups (the slot ids of four
+  // segments, then their sums, y beside the first ids) so that a column pays
+  // about three memory round trips, not one per segment; the sums are still
+  // added in slot order
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const int k0 = colptr[c], k1 = colptr[c + 1];
+  if (k1 == k0) return;
+  const float y0 = y[c];
+  float v = 0.0f;
+  int k = k0;
+  for (; k + 4 <= k1; k += 4) {
+    const int i0 = seg_ids[k], i1 = seg_ids[k + 1], i2 = seg_ids[k + 2], i3 = seg_ids[k + 3];
+    const float a0 = seg_val[i0], a1 = seg_val[i1], a2 = seg_val[i2], a3 = seg_val[i3];
+    v = (((v + a0) + a1) + a2) + a3;
   }
+  for (; k < k1; ++k) v += seg_val[seg_ids[k]];
+  y[c] = y0 + v;
 }
 
 // SYPRD over the panel format: each stored entry gives a x[i] x[j], twice
@@ -391,8 +403,8 @@ int panel_launch(const Tensor* t, const XT* x, float* y, hipStream_t s) {
       n, t->panel_rows, t->chunk_panel, t->chunk_tile_begin, t->chunk_tile_end, t->pcol,
       t->prow, t->pval, x, y, t->seg_tile0, t->work_seg);
   if (const int lrc = check_launch("ssymv panel kernel")) return lrc;
-  const int grid = static_cast<int>(std::min<int64_t>((n + 255) / 256, 8192));
-  panel_colsum_kernel<<<grid, 256, 0, s>>>(n, t->seg_colptr, t->seg_ids, t->work_seg, y);
+  panel_colsum_kernel<<<(n + 255) / 256, 256, 0, s>>>(n, t->seg_colptr, t->seg_ids, t->work_seg,
+                                                       y);
   return check_launch("ssymv panel column pass");
 }
 
