@@ -115,6 +115,13 @@ struct Tensor {
   int32_t* pcol = nullptr;
   uint16_t* prow = nullptr;
   float* pval = nullptr;
+  // The SSYMV kernels' index stream: per entry one word holding the column's
+  // offset from its step's base column (the high 32 - log2(H) bits) and the
+  // row in the panel (the low log2(H) bits); per step of 64 entries the base
+  // column, with bit 31 set where the step's columns span too much for the
+  // offsets (those steps read pcol and prow instead).
+  uint32_t* ppack = nullptr;
+  int32_t* pbase = nullptr;
   int nchunks = 0;
   int32_t* chunk_panel = nullptr;
   int32_t* chunk_tile_begin = nullptr;
@@ -298,7 +305,7 @@ struct ServeTensor {
   int32_t order;
   int32_t dim;    // n or I
   int32_t H;      // panel rows (matrix)
-  const void* p[5][5];  // matrix: p[0] = {pcol, prow, pval}; tensor: p[v] = view v's indices
+  const void* p[5][5];  // matrix: p[0] = {pcol, prow, pval, ppack, pbase}; tensor: p[v] = view v's indices
   const float* val[5];  // tensor: view values
   const ServeUnit* units;
 };

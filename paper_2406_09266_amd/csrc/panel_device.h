@@ -49,19 +49,44 @@ __device__ __forceinline__ void stage_slice(const XT* __restrict__ src, int coun
   }
 }
 
-// S steps of a tile's column, panel-row and value streams from entry base
-// (this lane's first entry), lane-strided: a step reads 64 consecutive
-// entries (coalesced).
+// S steps of a tile's packed index and value streams from entry base (this
+// lane's first entry), lane-strided: a step reads 64 consecutive entries
+// (coalesced); the steps' base columns (from step0, wave-uniform) are
+// scalar loads. Decoding waits for the loads, so it is left to
+// decode_panel_steps, which the caller runs when the unit starts.
 template <int S>
-__device__ __forceinline__ void load_panel_steps(int64_t base, const int32_t* __restrict__ pcol,
-                                                 const uint16_t* __restrict__ prow,
-                                                 const float* __restrict__ pval, int (&c)[S],
-                                                 int (&ro)[S], float (&a)[S]) {
+__device__ __forceinline__ void load_panel_steps(int64_t base, int64_t step0,
+                                                 const uint32_t* __restrict__ ppack,
+                                                 const int32_t* __restrict__ pbase,
+                                                 const float* __restrict__ pval, uint32_t (&pk)[S],
+                                                 int (&pb)[S], float (&a)[S]) {
 #pragma unroll
   for (int k = 0; k < S; ++k) {
-    c[k] = pcol[base + k * kWave];
-    ro[k] = prow[base + k * kWave];
+    pk[k] = ppack[base + k * kWave];
     a[k] = pval[base + k * kWave];
+    pb[k] = pbase[step0 + k];
+  }
+}
+
+// The column and panel row of each step's entry: base column plus offset
+// and the low bits; a step whose base has bit 31 set (columns spanning more
+// than the offsets hold, rare) reads them from pcol and prow instead.
+template <int S>
+__device__ __forceinline__ void decode_panel_steps(int64_t base, int hbits,
+                                                   const int32_t* __restrict__ pcol,
+                                                   const uint16_t* __restrict__ prow,
+                                                   const uint32_t (&pk)[S], const int (&pb)[S],
+                                                   int (&c)[S], int (&ro)[S]) {
+  const uint32_t rmask = (1u << hbits) - 1;
+#pragma unroll
+  for (int k = 0; k < S; ++k) {
+    if (pb[k] >= 0) {
+      c[k] = pb[k] + static_cast<int>(pk[k] >> hbits);
+      ro[k] = static_cast<int>(pk[k] & rmask);
+    } else {
+      c[k] = pcol[base + k * kWave];
+      ro[k] = prow[base + k * kWave];
+    }
   }
 }
 
@@ -100,6 +125,8 @@ __device__ __forceinline__ void ssymv_panel_chunk(int n, int H, int p, int tb, i
                                                   const int32_t* __restrict__ pcol,
                                                   const uint16_t* __restrict__ prow,
                                                   const float* __restrict__ pval,
+                                                  const uint32_t* __restrict__ ppack,
+                                                  const int32_t* __restrict__ pbase,
                                                   const XT* __restrict__ x, float* __restrict__ y,
                                                   float* s_rows, XT* s_x = nullptr,
                                                   const int32_t* __restrict__ seg_tile0 = nullptr,
@@ -111,8 +138,9 @@ __device__ __forceinline__ void ssymv_panel_chunk(int n, int H, int p, int tb, i
   if constexpr (kStageX) stage_slice(x + r0, min(H, n - r0), H, s_x);
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1);
-  const int w = threadIdx.x / kWave;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int nw = blockDim.x / kWave;
+  const int hbits = __builtin_ctz(static_cast<unsigned>(H));
   // the wave walks its tiles (tb + w, tb + w + nw, ...) in units of kSub
   // steps (half a tile, which keeps the registers of a unit, its prefetched
   // successor included, within 64 per lane); a unit's index and value
@@ -123,14 +151,13 @@ __device__ __forceinline__ void ssymv_panel_chunk(int n, int H, int p, int tb, i
   constexpr int kUnits = kV / kSub;
   const int first = tb + w;
   const int nunits = first < te ? (te - first + nw - 1) / nw * kUnits : 0;
-  const auto unit_base = [&](int u) {
-    return static_cast<int64_t>(first + (u / kUnits) * nw) * kTile + (u % kUnits) * kSub * kWave +
-           lane;
+  const auto unit_step = [&](int u) {  // the unit's first step
+    return static_cast<int64_t>(first + (u / kUnits) * nw) * kV + (u % kUnits) * kSub;
   };
-  int c[kSub];
-  int ro[kSub];
+  uint32_t pk[kSub];
+  int pb[kSub];
   float a[kSub];
-  if (nunits > 0) load_panel_steps(unit_base(0), pcol, prow, pval, c, ro, a);
+  if (nunits > 0) load_panel_steps(unit_step(0) * kWave + lane, unit_step(0), ppack, pbase, pval, pk, pb, a);
   unsigned* const s_bits = reinterpret_cast<unsigned*>(s_rows);
   int carry_key = -1;
   float carry = 0.0f;
@@ -141,10 +168,13 @@ __device__ __forceinline__ void ssymv_panel_chunk(int n, int H, int p, int tb, i
   for (int u = 0; u < nunits; ++u) {
     const int tile = first + (u / kUnits) * nw;
     const int part = u % kUnits;
+    int c[kSub];
+    int ro[kSub];
+    decode_panel_steps(unit_step(u) * kWave + lane, hbits, pcol, prow, pk, pb, c, ro);
     // every gather of the unit is issued before the first update (a gather
     // behind a branch waits for all earlier memory operations, the atomics
-    // included); padding entries point at a valid diagonal position, so no
-    // gather needs a guard
+    // included); padding entries point at a valid column of the panel, so
+    // no gather needs a guard
     float xc[kSub];
     float xr[kSub];
 #pragma unroll
@@ -153,10 +183,11 @@ __device__ __forceinline__ void ssymv_panel_chunk(int n, int H, int p, int tb, i
       xr[k] = kStageX ? load_f32(s_x, ro[k]) : load_f32(x, r0 + ro[k]);
     }
     // the next unit's streams (the last unit reloads itself: no branch)
-    int cn[kSub];
-    int ron[kSub];
+    uint32_t pkn[kSub];
+    int pbn[kSub];
     float an[kSub];
-    load_panel_steps(unit_base(u + 1 < nunits ? u + 1 : u), pcol, prow, pval, cn, ron, an);
+    const int un = u + 1 < nunits ? u + 1 : u;
+    load_panel_steps(unit_step(un) * kWave + lane, unit_step(un), ppack, pbase, pval, pkn, pbn, an);
     if (part == 0) {  // a tile starts: no segment carried in
       carry_key = -1;
       carry = 0.0f;
@@ -231,8 +262,8 @@ __device__ __forceinline__ void ssymv_panel_chunk(int n, int H, int p, int tb, i
     }
 #pragma unroll
     for (int k = 0; k < kSub; ++k) {
-      c[k] = cn[k];
-      ro[k] = ron[k];
+      pk[k] = pkn[k];
+      pb[k] = pbn[k];
       a[k] = an[k];
     }
   }

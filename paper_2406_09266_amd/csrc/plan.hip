@@ -167,11 +167,30 @@ __global__ void panel_pad_kernel(int npanels, int H, const int32_t* __restrict__
   for (int p = blockIdx.x; p < npanels; p += gridDim.x) {
     const int64_t b = static_cast<int64_t>(pstart[p]) + counts[p];
     const int64_t e = pstart[p + 1];
+    // value 0 at row 0 of the panel and the panel's last column, so the
+    // entries stay sorted by column (a zero contribution to both sides)
     for (int64_t q = b + threadIdx.x; q < e; q += blockDim.x) {
-      pcol[q] = p * H;  // the panel's first row: a diagonal position, value 0
+      pcol[q] = pcol[b - 1];
       prow[q] = 0;
       pval[q] = 0.0f;
     }
+  }
+}
+
+// The packed index stream of the panel SSYMV (see Tensor::ppack): one thread
+// per entry; a step's columns are sorted, so its first is its base and its
+// last sets its span.
+__global__ void panel_pack_kernel(int64_t padded, int hbits, const int32_t* __restrict__ pcol,
+                                  const uint16_t* __restrict__ prow, uint32_t* __restrict__ ppack,
+                                  int32_t* __restrict__ pbase) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < padded;
+       e += stride) {
+    const int64_t s0 = e / kWave * kWave;
+    const int32_t base = pcol[s0];
+    const bool wide = static_cast<uint32_t>(pcol[s0 + kWave - 1] - base) >> (32 - hbits) != 0;
+    ppack[e] = wide ? 0u : (static_cast<uint32_t>(pcol[e] - base) << hbits) | prow[e];
+    if (e == s0) pbase[e / kWave] = wide ? static_cast<int32_t>(static_cast<uint32_t>(base) | 0x80000000u) : base;
   }
 }
 
@@ -542,6 +561,13 @@ int tensor_create_csr(int64_t n, int64_t nnz, const int32_t* rowptr, const int32
     panel_pad_kernel<<<std::min(P, 4096), 256, 0, s>>>(P, H, counts, d_pstart, t->pcol, t->prow,
                                                       t->pval);
     rc = check_launch("panel pad kernel");
+  }
+  if (!rc) rc = tensor_alloc(t, &t->ppack, ppos);
+  if (!rc) rc = tensor_alloc(t, &t->pbase, ppos / kWave);
+  if (!rc && ppos > 0) {
+    panel_pack_kernel<<<grid_for(ppos, 256), 256, 0, s>>>(ppos, hbits, t->pcol, t->prow, t->ppack,
+                                                          t->pbase);
+    rc = check_launch("panel pack kernel");
   }
   if (!rc && ppos > 0) rc = build_column_segments(t, s);
   // the calls' work buffers (see Tensor)

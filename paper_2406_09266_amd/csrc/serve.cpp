@@ -109,6 +109,8 @@ class GpuExecutor {
       d.p[0][0] = t->pcol;
       d.p[0][1] = t->prow;
       d.p[0][2] = t->pval;
+      d.p[0][3] = t->ppack;
+      d.p[0][4] = t->pbase;
     } else {
       for (int v = 0; v < t->order; ++v) {
         for (int q = 0; q < t->order; ++q) d.p[v][q] = t->vidx[v][q];

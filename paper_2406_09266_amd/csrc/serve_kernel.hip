@@ -108,12 +108,14 @@ __global__ __launch_bounds__(kServeBlock) void serve_ssymv_kernel(StepArgs a) {
   const auto* pcol = uni_ptr(static_cast<const int32_t*>(t->p[0][0]));
   const auto* prow = uni_ptr(static_cast<const uint16_t*>(t->p[0][1]));
   const auto* pval = uni_ptr(static_cast<const float*>(t->p[0][2]));
+  const auto* ppack = uni_ptr(static_cast<const uint32_t*>(t->p[0][3]));
+  const auto* pbase = uni_ptr(static_cast<const int32_t*>(t->p[0][4]));
   const int dim = uni(t->dim), H = uni(t->H);
   if (r.dtype == SYSTEC_F32)
-    ssymv_panel_chunk<float>(dim, H, u.a, u.b, u.c, pcol, prow, pval,
+    ssymv_panel_chunk<float>(dim, H, u.a, u.b, u.c, pcol, prow, pval, ppack, pbase,
                              static_cast<const float*>(r.in), r.out, s_lds);
   else  // BF16 x: with kStageX the panel's x slice follows the row sums in LDS
-    ssymv_panel_chunk<uint16_t, kStageX>(dim, H, u.a, u.b, u.c, pcol, prow, pval,
+    ssymv_panel_chunk<uint16_t, kStageX>(dim, H, u.a, u.b, u.c, pcol, prow, pval, ppack, pbase,
                                          static_cast<const uint16_t*>(r.in), r.out, s_lds,
                                          reinterpret_cast<uint16_t*>(s_lds + H));
 }

@@ -136,12 +136,14 @@ __global__ __launch_bounds__(kPanelThreads) void ssymv_panel_kernel(
     int n, int H, const int32_t* __restrict__ chunk_panel,
     const int32_t* __restrict__ chunk_tile_begin, const int32_t* __restrict__ chunk_tile_end,
     const int32_t* __restrict__ pcol, const uint16_t* __restrict__ prow,
-    const float* __restrict__ pval, const XT* __restrict__ x, float* __restrict__ y,
+    const float* __restrict__ pval, const uint32_t* __restrict__ ppack,
+    const int32_t* __restrict__ pbase, const XT* __restrict__ x, float* __restrict__ y,
     const int32_t* __restrict__ seg_tile0, float* __restrict__ seg_out) {
   extern __shared__ float s_rows[];  // the panel's row sums
   const int chunk = blockIdx.x;
   ssymv_panel_chunk<XT, kStageX, true>(n, H, chunk_panel[chunk], chunk_tile_begin[chunk],
-                                       chunk_tile_end[chunk], pcol, prow, pval, x, y, s_rows,
+                                       chunk_tile_end[chunk], pcol, prow, pval, ppack, pbase, x,
+                                       y, s_rows,
                                        reinterpret_cast<XT*>(s_rows + H), seg_tile0, seg_out);
 }
 
@@ -401,7 +403,7 @@ int panel_launch(const Tensor* t, const XT* x, float* y, hipStream_t s) {
   const int n = static_cast<int>(t->dim);
   ssymv_panel_kernel<XT, kStageX><<<dim3(t->nchunks), dim3(kPanelThreads), lds, s>>>(
       n, t->panel_rows, t->chunk_panel, t->chunk_tile_begin, t->chunk_tile_end, t->pcol,
-      t->prow, t->pval, x, y, t->seg_tile0, t->work_seg);
+      t->prow, t->pval, t->ppack, t->pbase, x, y, t->seg_tile0, t->work_seg);
   if (const int lrc = check_launch("ssymv panel kernel")) return lrc;
   panel_colsum_kernel<<<(n + 255) / 256, 256, 0, s>>>(n, t->seg_colptr, t->seg_ids, t->work_seg,
                                                        y);
