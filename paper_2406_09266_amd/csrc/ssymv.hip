@@ -187,37 +187,58 @@ __global__ __launch_bounds__(kPanelThreads) void syprd_panel_kernel(
     int n, int H, const int32_t* __restrict__ chunk_panel,
     const int32_t* __restrict__ chunk_tile_begin, const int32_t* __restrict__ chunk_tile_end,
     const int32_t* __restrict__ pcol, const uint16_t* __restrict__ prow,
-    const float* __restrict__ pval, const XT* __restrict__ x, float* __restrict__ partial) {
+    const float* __restrict__ pval, const uint32_t* __restrict__ ppack,
+    const int32_t* __restrict__ pbase, const XT* __restrict__ x, float* __restrict__ partial) {
   extern __shared__ __align__(16) unsigned char s_dyn[];
   XT* s_x = reinterpret_cast<XT*>(s_dyn);
   __shared__ float s_part[kPanelThreads / kWave];
   const int chunk = blockIdx.x;
   const int r0 = chunk_panel[chunk] * H;
   const int tb = chunk_tile_begin[chunk], te = chunk_tile_end[chunk];
-  for (int i = threadIdx.x; i < H; i += blockDim.x) s_x[i] = r0 + i < n ? x[r0 + i] : XT(0);
+  stage_slice(x + r0, min(H, n - r0), H, s_x);
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1);
-  const int w = threadIdx.x / kWave;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int nw = blockDim.x / kWave;
+  const int hbits = __builtin_ctz(static_cast<unsigned>(H));
+  // the wave's tiles in halves, the next half's streams loaded behind the
+  // current half's gathers (as in the panel SSYMV)
+  constexpr int kSub = kV / 2;
+  constexpr int kUnits = kV / kSub;
+  const int first = tb + w;
+  const int nunits = first < te ? (te - first + nw - 1) / nw * kUnits : 0;
+  const auto unit_step = [&](int u) {
+    return static_cast<int64_t>(first + (u / kUnits) * nw) * kV + (u % kUnits) * kSub;
+  };
+  uint32_t pk[kSub];
+  int pb[kSub];
+  float a[kSub];
+  if (nunits > 0)
+    load_panel_steps(unit_step(0) * kWave + lane, unit_step(0), ppack, pbase, pval, pk, pb, a);
   float sum = 0.0f;
-  for (int tile = tb + w; tile < te; tile += nw) {
-    const int64_t base = static_cast<int64_t>(tile) * kTile + lane;
-    int c[kV];
-    int ro[kV];
-    float a[kV];
+  for (int u = 0; u < nunits; ++u) {
+    int c[kSub];
+    int ro[kSub];
+    decode_panel_steps(unit_step(u) * kWave + lane, hbits, pcol, prow, pk, pb, c, ro);
+    float xc[kSub];
 #pragma unroll
-    for (int k = 0; k < kV; ++k) {  // coalesced: a step reads 64 consecutive entries
-      c[k] = pcol[base + k * kWave];
-      ro[k] = prow[base + k * kWave];
-      a[k] = pval[base + k * kWave];
-    }
-    float xc[kV];
+    for (int k = 0; k < kSub; ++k) xc[k] = load_f32(x, c[k]);  // padding: a valid position
+    uint32_t pkn[kSub];
+    int pbn[kSub];
+    float an[kSub];
+    const int un = u + 1 < nunits ? u + 1 : u;
+    load_panel_steps(unit_step(un) * kWave + lane, unit_step(un), ppack, pbase, pval, pkn, pbn,
+                     an);
 #pragma unroll
-    for (int k = 0; k < kV; ++k) xc[k] = load_f32(x, c[k]);  // padding: a valid position
-#pragma unroll
-    for (int k = 0; k < kV; ++k) {
+    for (int k = 0; k < kSub; ++k) {
       const float f = c[k] != r0 + ro[k] ? 2.0f : 1.0f;
       sum += f * a[k] * load_f32(s_x, ro[k]) * xc[k];
+    }
+#pragma unroll
+    for (int k = 0; k < kSub; ++k) {
+      pk[k] = pkn[k];
+      pb[k] = pbn[k];
+      a[k] = an[k];
     }
   }
   sum = wave_sum(sum);
@@ -479,11 +500,11 @@ int syprd_panel_call(const Tensor* t, const void* x, systec_dtype xdt, double* o
       if (xdt == SYSTEC_F32)
         syprd_panel_kernel<float><<<dim3(t->nchunks), dim3(kPanelThreads), lds, s>>>(
             n, t->panel_rows, t->chunk_panel, t->chunk_tile_begin, t->chunk_tile_end, t->pcol,
-            t->prow, t->pval, static_cast<const float*>(x), partial);
+            t->prow, t->pval, t->ppack, t->pbase, static_cast<const float*>(x), partial);
       else
         syprd_panel_kernel<uint16_t><<<dim3(t->nchunks), dim3(kPanelThreads), lds, s>>>(
             n, t->panel_rows, t->chunk_panel, t->chunk_tile_begin, t->chunk_tile_end, t->pcol,
-            t->prow, t->pval, static_cast<const uint16_t*>(x), partial);
+            t->prow, t->pval, t->ppack, t->pbase, static_cast<const uint16_t*>(x), partial);
       rc = check_launch("syprd panel kernel");
     }
   }
