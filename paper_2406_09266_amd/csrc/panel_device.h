@@ -62,8 +62,8 @@ __device__ __forceinline__ void load_panel_steps(int64_t base, int64_t step0,
                                                  int (&pb)[S], float (&a)[S]) {
 #pragma unroll
   for (int k = 0; k < S; ++k) {
-    pk[k] = ppack[base + k * kWave];
-    a[k] = pval[base + k * kWave];
+    pk[k] = __builtin_nontemporal_load(ppack + base + k * kWave);
+    a[k] = __builtin_nontemporal_load(pval + base + k * kWave);
     pb[k] = pbase[step0 + k];
   }
 }
