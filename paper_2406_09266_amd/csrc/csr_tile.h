@@ -108,8 +108,8 @@ __device__ __forceinline__ bool load_tile_split(const int32_t* __restrict__ rowp
   for (int q = 0; q < kV; ++q) {
     const int p = q * kWave + lane;
     if (p < cnt) {
-      S.col[p] = col[j0 + p];
-      S.val[p] = val[j0 + p];
+      S.col[p] = __builtin_nontemporal_load(col + j0 + p);  // read once
+      S.val[p] = __builtin_nontemporal_load(val + j0 + p);
     }
   }
   wave_sync();
