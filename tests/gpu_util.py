@@ -1,6 +1,8 @@
 """Helpers shared by the GPU tests (not collected: no test_ prefix)."""
 import numpy as np
 
+from paper_2406_09266_amd import synth
+
 
 def dev(a, dtype=None):
     import torch
@@ -50,3 +52,26 @@ def assert_elementwise(got, want, scale, tol, what=""):
             f"{what}: {int(bad.sum())} of {bad.size} elements off; first flat index {i}: "
             f"got {got.reshape(-1)[i]!r} want {want.reshape(-1)[i]!r} "
             f"scale {scale.reshape(-1)[i]!r} (tol {tol})")
+
+
+def wide_step_matrix():
+    """A matrix whose panels mix narrow and wide steps: the first panel is a
+    dense band (64 consecutive entries span a few hundred columns), the rest
+    hold a few rows with entries spread over the whole column range, so a
+    step of 64 sorted entries (padding included) spans more than 2^19
+    columns and the kernels take its columns from the unpacked stream."""
+    n = 2_000_000
+    rng = np.random.Generator(np.random.PCG64(61))
+    rows, cols = [], []
+    for i in range(4000):  # band rows: 12 entries each within 4,000 columns
+        c = np.unique(i + rng.integers(0, 4000, 12))
+        rows.append(np.full(c.size, i)); cols.append(c)
+    for i in range(5000, n, 6007):  # sparse rows: the diagonal and 3 far columns
+        c = np.unique(np.r_[i, rng.integers(i, n, 3)])
+        rows.append(np.full(c.size, i)); cols.append(c)
+    r = np.concatenate(rows).astype(np.int64); c = np.concatenate(cols).astype(np.int64)
+    order = np.lexsort((c, r)); r, c = r[order], c[order]
+    rowptr = np.zeros(n + 1, np.int64); np.add.at(rowptr, r + 1, 1); rowptr = np.cumsum(rowptr)
+    return {"n": n, "rowptr": rowptr.astype(np.int32), "col": c.astype(np.int32),
+            "val": synth.dense_uniform(c.size, seed=62, low=0.0, high=1.0),
+            "x": synth.dense_uniform(n, seed=63)}

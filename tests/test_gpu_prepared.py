@@ -7,7 +7,7 @@ import oracle
 import paper_2406_09266_amd as systec
 from paper_2406_09266_amd import synth
 
-from gpu_util import assert_elementwise, dev, f32, rel_err
+from gpu_util import assert_elementwise, dev, f32, rel_err, wide_step_matrix
 
 pytestmark = pytest.mark.gpu
 TOL32 = 1e-5
@@ -157,29 +157,6 @@ def test_prepared_ssymv_empty_rows_and_panels():
     assert torch.count_nonzero(ye).item() == 0
 
 
-def _wide_step_matrix():
-    """A matrix whose panels mix narrow and wide steps: the first panel is a
-    dense band (64 consecutive entries span a few hundred columns), the rest
-    hold a few rows with entries spread over the whole column range, so a
-    step of 64 sorted entries (padding included) spans more than 2^19
-    columns and the kernels take its columns from the unpacked stream."""
-    n = 2_000_000
-    rng = np.random.Generator(np.random.PCG64(61))
-    rows, cols = [], []
-    for i in range(4000):  # band rows: 12 entries each within 4,000 columns
-        c = np.unique(i + rng.integers(0, 4000, 12))
-        rows.append(np.full(c.size, i)); cols.append(c)
-    for i in range(5000, n, 6007):  # sparse rows: the diagonal and 3 far columns
-        c = np.unique(np.r_[i, rng.integers(i, n, 3)])
-        rows.append(np.full(c.size, i)); cols.append(c)
-    r = np.concatenate(rows).astype(np.int64); c = np.concatenate(cols).astype(np.int64)
-    order = np.lexsort((c, r)); r, c = r[order], c[order]
-    rowptr = np.zeros(n + 1, np.int64); np.add.at(rowptr, r + 1, 1); rowptr = np.cumsum(rowptr)
-    return {"n": n, "rowptr": rowptr.astype(np.int32), "col": c.astype(np.int32),
-            "val": synth.dense_uniform(c.size, seed=62, low=0.0, high=1.0),
-            "x": synth.dense_uniform(n, seed=63)}
-
-
 def _wide_steps(m, H=8192):
     """Steps of 64 entries in the vertex-order panel layout (panels of H rows,
     entries sorted by column, padded to 512 with the last column) whose
@@ -198,7 +175,7 @@ def _wide_steps(m, H=8192):
 @pytest.mark.parametrize("xdtype", ["f32", "bf16"])
 def test_prepared_wide_steps(relabel, xdtype):
     """SSYMV and SYPRD where some steps' columns overflow the packed offsets."""
-    m = _wide_step_matrix()
+    m = wide_step_matrix()
     assert _wide_steps(m) > 100  # the fallback path is exercised (vertex order)
     print(f"prepared wide steps relabel={relabel} x={xdtype} n={m['n']} nnz={m['col'].size}",
           flush=True)

@@ -9,7 +9,7 @@ import oracle
 import paper_2406_09266_amd as systec
 from paper_2406_09266_amd import synth
 
-from gpu_util import dev, f32, rel_err
+from gpu_util import dev, f32, rel_err, wide_step_matrix
 
 pytestmark = pytest.mark.gpu
 TOL32 = 1e-5
@@ -133,6 +133,24 @@ def test_relabeled_matrices_are_served(bf16, step_work):
     for r, (_, o) in zip(reqs, outs):
         assert rel_err(o.cpu().numpy(), _oracle(mats, tens, r, bf16)) <= TOL32
     assert st["completed"] == 16 and st["failed"] == 0
+
+
+@pytest.mark.parametrize("relabel", [False, True])
+def test_wide_steps_are_served(relabel):
+    """A matrix with steps whose columns overflow the packed offsets (the
+    kernels read those steps' columns unpacked), served in FP32 and BF16."""
+    m = wide_step_matrix()
+    reqs = [(0, synth.dense_uniform(m["n"], seed=2000 + k), 1) for k in range(4)]
+    with systec.Server(budget_bytes=8 << 30, max_slots=4, step_work_nnz=1 << 14) as srv:
+        ids = [srv.register(systec.Tensor.from_csr(dev(m["rowptr"]), dev(m["col"]),
+                                                   dev(m["val"].astype(np.float32)),
+                                                   relabel=relabel))]
+        outs = [(_submit(srv, ids, [m], [], r, k % 2 == 1), k % 2 == 1)
+                for k, r in enumerate(reqs)]
+        for (rid, _), _ in outs:
+            srv.wait(rid, 60_000_000)
+    for r, ((_, o), bf16) in zip(reqs, outs):
+        assert rel_err(o.cpu().numpy(), _oracle([m], [], r, bf16)) <= TOL32
 
 
 def test_relabeled_request_counts_its_scratch():
