@@ -21,6 +21,7 @@
 // wave and one atomic per run of equal columns).
 #include "common.h"
 #include "csr_tile.h"
+#include "panel_device.h"
 #include "wave_ops.h"
 
 namespace systec {
@@ -131,10 +132,10 @@ __global__ __launch_bounds__(kPanelThreads) void bf_panel_kernel(
   const int r0 = chunk_panel[chunk] * H;
   const int tb = chunk_tile_begin[chunk], te = chunk_tile_end[chunk];
   const int64_t vend = chunk_valid_end[chunk];
-  for (int i = threadIdx.x; i < H; i += blockDim.x) {
-    s_min[i] = kKeyInf;
-    s_d[i] = r0 + i < n ? d[r0 + i] : INFINITY;
-  }
+  for (int i = threadIdx.x; i < H; i += blockDim.x) s_min[i] = kKeyInf;
+  // the slice of d with every load of a thread issued before its LDS writes
+  // (rows at or past n, zero-filled, hold no entries)
+  stage_slice(d + r0, min(H, n - r0), H, s_d);
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1);
   const int w = threadIdx.x / kWave;
