@@ -88,13 +88,21 @@ __global__ __launch_bounds__(kBinThreads) void bucket_count_kernel(
       if (d1 == total) split[tile + 1] = i1;  // the last tile
     }
     const int j0 = static_cast<int>(d0 - i0);
-    const int j1 = static_cast<int>(d1 - i1);
-    for (int j0w = j0; j0w < j1; j0w += kWave) {  // wave-uniform
-      const int j = j0w + lane;
-      const int c = j < j1 ? col[j] : -1;
+    const int cnt = static_cast<int>(d1 - i1) - j0;  // at most kTile entries
+    // all of the tile's column loads first, then the counter updates (a
+    // load behind each update would wait for it)
+    int cc[kV];
+#pragma unroll
+    for (int q = 0; q < kV; ++q) {
+      const int p = q * kWave + lane;
+      cc[q] = p < cnt ? col[j0 + p] : -1;
+    }
+#pragma unroll
+    for (int q = 0; q < kV; ++q) {
+      if (q * kWave >= cnt) break;  // wave-uniform
       // columns outside [0, n) are left out, as in the binning pass
-      const bool ok = static_cast<unsigned>(c) < static_cast<unsigned>(n);
-      run_atomic_add(s_cnt, ok ? (c >> kBucketBits) : -1, ok, lane);
+      const bool ok = static_cast<unsigned>(cc[q]) < static_cast<unsigned>(n);
+      run_atomic_add(s_cnt, ok ? (cc[q] >> kBucketBits) : -1, ok, lane);
     }
   }
   __syncthreads();
