@@ -252,7 +252,7 @@ __device__ __forceinline__ void mttkrp_view_tile_slot(int t, int e0, int e1, con
 // a multiple of V and B aligned to V elements (rows stay aligned).
 
 // entries in flight per lane group (a group already covers a whole row)
-constexpr int kUnrollVec = 2;
+constexpr int kUnrollVec = 4;
 
 // Words (4 bytes) per lane for V elements of BT.
 template <typename BT, int V>
