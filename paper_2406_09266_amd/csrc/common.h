@@ -92,7 +92,8 @@ int expand_coo(int order, int64_t I, int64_t nnz, const int32_t* const* idx, con
 // A matrix in the symmetric panel format: the stored upper triangle cut into
 // panels of H consecutive rows; inside a panel the entries are sorted by
 // (column, row) and padded to a multiple of kPanelTile entries (padding:
-// value 0 on the panel's first diagonal position). The kernel keeps the
+// value 0 at the panel's first row and last column, so the columns stay
+// sorted). The kernel keeps the
 // panel's row sums in LDS and reduces the column side by segments.
 // A tensor as slot views: for each slot t, the canonical entries whose slot t
 // starts a run of equal indices, sorted by their slot-t index (stable), so
