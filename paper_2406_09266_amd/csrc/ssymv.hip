@@ -436,9 +436,9 @@ int panel_call(const Tensor* t, const void* x, systec_dtype xdt, float* y, bool 
                hipStream_t s) {
   int rc = y_clear ? SYSTEC_OK : launch_fill_f32(y, t->dim, s);
   if (rc != SYSTEC_OK) return rc;
-  if (xdt == SYSTEC_F32) return panel_launch<float, false>(t, static_cast<const float*>(x), y, s);
-  // BF16 x: the panel's slice of x goes to LDS beside the row sums when the
-  // device allows that much per workgroup (8192 rows: 48 KiB)
+  // the panel's slice of x goes to LDS beside the row sums when the device
+  // allows that much per workgroup (8192 rows: 48 KiB with BF16 x, 64 KiB
+  // with FP32 x)
   int dev = 0;
   int limit = 0;
   rc = check_hip(hipGetDevice(&dev), "hipGetDevice");
@@ -446,10 +446,17 @@ int panel_call(const Tensor* t, const void* x, systec_dtype xdt, float* y, bool 
     rc = check_hip(hipDeviceGetAttribute(&limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev),
                    "hipDeviceGetAttribute(max shared memory)");
   if (rc) return rc;
-  const size_t staged = static_cast<size_t>(t->panel_rows) * (sizeof(float) + sizeof(uint16_t));
+  const size_t rows = static_cast<size_t>(t->panel_rows) * sizeof(float);
+  if (xdt == SYSTEC_F32) {
+    const float* xf = static_cast<const float*>(x);
+    return rows + static_cast<size_t>(t->panel_rows) * sizeof(float) <= static_cast<size_t>(limit)
+               ? panel_launch<float, true>(t, xf, y, s)
+               : panel_launch<float, false>(t, xf, y, s);
+  }
   const uint16_t* xb = static_cast<const uint16_t*>(x);
-  return staged <= static_cast<size_t>(limit) ? panel_launch<uint16_t, true>(t, xb, y, s)
-                                              : panel_launch<uint16_t, false>(t, xb, y, s);
+  return rows + static_cast<size_t>(t->panel_rows) * sizeof(uint16_t) <= static_cast<size_t>(limit)
+             ? panel_launch<uint16_t, true>(t, xb, y, s)
+             : panel_launch<uint16_t, false>(t, xb, y, s);
 }
 
 }  // namespace
