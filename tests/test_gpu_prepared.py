@@ -136,6 +136,28 @@ def test_prepared_ssymv_reports_vertex_order(relabel):
 
 
 
+@pytest.mark.parametrize("xdtype", ["f32", "bf16"])
+def test_prepared_ssymv_unaligned_x(xdtype):
+    """x one element past a 16-byte boundary: the panels' x slices are staged
+    element by element instead of in 16-byte pieces."""
+    import torch
+    m = synth.ssymv_uniform(40001, 9, seed=59)
+    A = systec.Tensor.from_csr(dev(m["rowptr"]), dev(m["col"]), dev(m["val"].astype(np.float32)),
+                               relabel=False)  # x reaches the panel kernels as given
+    x, xref = _x(m, xdtype)
+    buf = torch.empty(m["n"] + 1, dtype=x.dtype, device="cuda")
+    buf[1:] = x
+    xu = buf[1:]
+    assert xu.data_ptr() % 16 != 0
+    y = A.ssymv(xu).cpu().numpy()
+    want, _ = oracle.ssymv(m["n"], m["rowptr"], m["col"], f32(m["val"]), xref)
+    assert rel_err(y, want) <= TOL32
+    s = A.syprd(xu).item()
+    swant, scale, _ = oracle.syprd(m["n"], m["rowptr"], m["col"], f32(m["val"]), xref)
+    assert abs(s - swant) <= TOL32 * scale
+    A.close()
+
+
 def test_prepared_ssymv_empty_rows_and_panels():
     import torch
     # rows only in the last panel; earlier panels empty
