@@ -256,10 +256,20 @@ __global__ __launch_bounds__(kPanelThreads) void syprd_panel_kernel(
 template <typename XT>
 __global__ void permute_in_kernel(int n, const int32_t* __restrict__ perm, const XT* __restrict__ x,
                                   XT* __restrict__ xp, float* __restrict__ yp) {
+  // two elements per thread: both gathers in flight, and the index loads,
+  // stores and clears of a wave 8 bytes a lane (n odd: the last one alone)
   const int stride = gridDim.x * blockDim.x;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    xp[i] = x[perm[i]];
-    if (yp) yp[i] = 0.0f;  // the panels accumulate into yp
+  const int pairs = n / 2;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < pairs; k += stride) {
+    const int2 p = reinterpret_cast<const int2*>(perm)[k];
+    const XT a = x[p.x], b = x[p.y];
+    xp[2 * k] = a;
+    xp[2 * k + 1] = b;
+    if (yp) reinterpret_cast<float2*>(yp)[k] = make_float2(0.0f, 0.0f);  // the panels accumulate
+  }
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    xp[n - 1] = x[perm[n - 1]];
+    if (yp) yp[n - 1] = 0.0f;
   }
 }
 
@@ -267,7 +277,14 @@ __global__ void permute_in_kernel(int n, const int32_t* __restrict__ perm, const
 __global__ void permute_out_kernel(int n, const int32_t* __restrict__ inv,
                                    const float* __restrict__ yp, float* __restrict__ y) {
   const int stride = gridDim.x * blockDim.x;
-  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride) y[j] = yp[inv[j]];
+  const int pairs = n / 2;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < pairs; k += stride) {
+    const int2 q = reinterpret_cast<const int2*>(inv)[k];
+    const float a = yp[q.x], b = yp[q.y];
+    y[2 * k] = a;  // y is the caller's: 4-byte aligned only
+    y[2 * k + 1] = b;
+  }
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) y[n - 1] = yp[inv[n - 1]];
 }
 
 __global__ void fill_f32_kernel(float* __restrict__ p, int64_t n) {
